@@ -1,0 +1,108 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+Holds no arithmetic of the method: only problem descriptions and random
+draws.  Inputs are shaped like the paper's experiments (screened Poisson on a
+rectangle, uniform or given breakpoints, random Legendre right-hand sides;
+Sec. 4 and Sec. 5 experiments use "random samples" for f).
+
+Right-hand side recipe: the piecewise tensor-Legendre coefficients of f are
+
+    F[(kx, ex), (ky, ey)] = Z * (1 + kx)^-2 * (1 + ky)^-2,   Z ~ N(0, 1) i.i.d.,
+
+indexed degree-major (row kx*nx + ex, column ky*ny + ey), drawn with
+numpy.random.default_rng(seed).standard_normal in row-major order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Problem:
+    """One screened-Poisson problem on [ax, bx] x [ay, by]."""
+
+    name: str
+    nx: int
+    px: int
+    ny: int
+    py: int
+    omega2: float
+    bc: str            # "dirichlet" or "neumann" (both axes)
+    tol: float
+    seed: int
+    ax: float = 0.0
+    bx: float = 1.0
+    ay: float = 0.0
+    by: float = 1.0
+
+    def dims(self):
+        def N(n, p):
+            return n * p - 1 if self.bc == "dirichlet" else n * p + 1
+        return N(self.nx, self.px), N(self.ny, self.py)
+
+    def leg_dims(self):
+        return (self.px + 1) * self.nx, (self.py + 1) * self.ny
+
+
+def legendre_rhs(nx: int, px: int, ny: int, py: int, seed: int) -> np.ndarray:
+    """F of shape ((px+1) nx, (py+1) ny), FP64, per the module recipe."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal(((px + 1) * nx, (py + 1) * ny))
+    kx = np.arange((px + 1) * nx) // nx
+    ky = np.arange((py + 1) * ny) // ny
+    return Z * (1.0 + kx)[:, None] ** -2 * (1.0 + ky)[None, :] ** -2
+
+
+# The problem families (uniform meshes, both axes share the BC):
+CFG_SMALL = Problem("poisson_n4_p8_dirichlet", 4, 8, 4, 8, 0.0, "dirichlet", 1e-12, 0)
+CFG_FP64_1K = Problem("screened_n32_p32_dirichlet_w2_10", 32, 32, 32, 32, 10.0, "dirichlet",
+                      1e-12, 1, ax=-1.0, bx=1.0, ay=0.0, by=2.0)
+CFG_MIXED_4K_D = Problem("poisson_n64_p64_dirichlet", 64, 64, 64, 64, 0.0, "dirichlet", 1e-10, 2)
+CFG_MIXED_4K_N = Problem("screened_n64_p64_neumann_w2_1", 64, 64, 64, 64, 1.0, "neumann", 1e-10, 2)
+CFG_VARCOEF_1K = Problem("varcoef_n32_p32_dirichlet", 32, 32, 32, 32, 0.0, "dirichlet", 1e-10, 4)
+
+PROBLEMS = {p.name: p for p in (CFG_SMALL, CFG_FP64_1K, CFG_MIXED_4K_D, CFG_MIXED_4K_N,
+                                CFG_VARCOEF_1K)}
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchInstance:
+    nx: int
+    px: int
+    ny: int
+    py: int
+    omega2: float
+    bc: str
+    seed: int
+
+
+def draw_batch(count: int = 512, seed: int = 3, nmax_dofs: int = 2049):
+    """Independent instances: per axis n in {4,8,16,32,64}, p in {8,16,32,64,128},
+    redrawn until n p + 1 <= nmax_dofs; omega^2 log-uniform in [1e-2, 1e3];
+    BC Dirichlet or Neumann with equal probability, the same on both axes."""
+    rng = np.random.default_rng(seed)
+    ns = np.array([4, 8, 16, 32, 64])
+    ps = np.array([8, 16, 32, 64, 128])
+    out = []
+    for i in range(count):
+        def axis():
+            while True:
+                n, p = int(rng.choice(ns)), int(rng.choice(ps))
+                if n * p + 1 <= nmax_dofs:
+                    return n, p
+        nx, px = axis()
+        ny, py = axis()
+        omega2 = float(10.0 ** rng.uniform(-2.0, 3.0))
+        bc = "dirichlet" if rng.random() < 0.5 else "neumann"
+        out.append(BatchInstance(nx, px, ny, py, omega2, bc, seed * 100003 + i))
+    return out
+
+
+def manufactured_sin(omega2: float):
+    """u = sin(pi x) sin(pi y), f = (2 pi^2 + omega^2) u, as separable factors."""
+    def fx(x):
+        return np.sin(math.pi * x)
+    return fx, fx, 2.0 * math.pi ** 2 + omega2
