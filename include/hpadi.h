@@ -1,0 +1,169 @@
+/*
+ * hpadi — ADI solver for the tensor-product hp-FEM discretisation of the
+ * screened Poisson equation on a rectangle, for AMD MI355X (gfx950).
+ *
+ * Method: Knook, Olver and Papadopoulos, "Quasi-optimal complexity hp-FEM
+ * for the Poisson equation on a rectangle" (arXiv 2402.11299).
+ *
+ *   -Laplace(u) + omega^2 u = f  on [ax,bx] x [ay,by], zero Dirichlet or zero
+ *   Neumann conditions (Sec. 1 eq. poisson, Sec. 3.3), discretised in the
+ *   hat + integrated-Legendre bubble basis (Sec. 2) as the generalised
+ *   Sylvester equation (Sec. 3.2 eq. 2d:poisson)
+ *
+ *       A_Y^x U M^y + M^x U A_Y^y = G,   A_Y = K + (omega^2/2) M,   G = T_x F T_y^T,
+ *
+ *   and solved with the generalised ADI of Sec. 5 (Alg. 2), whose shifted
+ *   1D systems are factorised by the reverse Cholesky of Sec. 4 (Alg. 1).
+ *
+ * Conventions for every call:
+ *  - Return value: HPADI_OK (0) or a negative status; hpadi_strerror() gives
+ *    text.  No C++ exception crosses this interface.
+ *  - 1D coefficient order is the paper's degree-major order (Sec. 2.2):
+ *    [hats | W_0 of elements 1..n | W_1 of elements 1..n | ... | W_{p-2}];
+ *    Dirichlet keeps the interior hats (vertices 1..n-1), Neumann all n+1
+ *    hats.  N = n p - 1 (Dirichlet) or n p + 1 (Neumann).  Piecewise
+ *    Legendre coefficients (degrees 0..p) are ordered [P_0 block | P_1 block
+ *    | ...], Nleg = (p+1) n.
+ *  - 2D arrays are row-major: entry (i, j) at ptr[i*ld + j], i the x index
+ *    (rows, Sec. 3.2), j the y index; ld >= number of columns.
+ *  - Pointers named *_dev are device (HIP) memory owned by the caller;
+ *    pointers named host/buf are host memory owned by the caller.  Handles
+ *    and all device scratch they need are owned by the library and released
+ *    by the matching *_destroy.
+ *  - Device work is stream-ordered on the plan's stream (NULL = the default
+ *    stream).  Calls that return data to the host (statistics, exports)
+ *    synchronise that stream.  A handle is not thread-safe; distinct handles
+ *    are independent.
+ */
+#ifndef HPADI_H
+#define HPADI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HPADI_OK = 0,
+    HPADI_EINVAL = -1,     /* invalid argument or size */
+    HPADI_ENOTSPD = -2,    /* a factorisation met a pivot <= 0 (or NaN) */
+    HPADI_ESINGULAR = -3,  /* Neumann with omega^2 <= 0: A_Y is singular */
+    HPADI_EINTERVAL = -4,  /* spectral intervals not disjoint (assumption P2 of Sec. 5) */
+    HPADI_ENOCONV = -5,    /* tolerance not reached; the best iterate is returned */
+    HPADI_EHIP = -6,       /* a HIP runtime call failed */
+    HPADI_ENOMEM = -7      /* device or host allocation failed */
+};
+
+enum { HPADI_DIRICHLET = 0, HPADI_NEUMANN = 1 };
+enum { HPADI_FP64 = 0, HPADI_MIXED = 1 };
+
+typedef struct hpadi_op1d_s* hpadi_op1d;
+typedef struct hpadi_plan_s* hpadi_plan;
+
+/* Per-solve statistics (host struct filled by hpadi_solve). */
+typedef struct {
+    int J;               /* ADI iterations per inner solve */
+    int rounds;          /* refinement rounds (1 for FP64) */
+    int iters;           /* total ADI iterations run */
+    int status;          /* HPADI_OK or HPADI_ENOCONV */
+    double interval[4];  /* [a, b, c, d] used by the plan */
+    double est_rel_err;  /* estimated relative error of U (mixed mode) */
+    double res_rel;      /* last FP64 relative residual ||G - A U|| / ||G|| (mixed mode) */
+    double t_ms[4];      /* reserved */
+} hpadi_stats;
+
+/* Options for hpadi_plan_create_ex (zero-initialise, then set fields). */
+typedef struct {
+    double inner_tol;   /* mixed mode: tolerance of each FP32 ADI solve (0 = 1e-5) */
+    int max_rounds;     /* mixed mode: refinement round limit (0 = 8) */
+    int lines_col;      /* column pass: lines per workgroup (0 = automatic) */
+    int lines_row;      /* row pass: lines per workgroup (0 = automatic) */
+    int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
+    int reserved[3];
+} hpadi_options;
+
+/* ---- 1D operators (Sec. 2, Sec. 3.1, App. A) -------------------------- */
+
+/* Mesh [a, b] with n elements of degree p (p >= 1, n >= 1).  breaks: host
+ * array of n+1 increasing points, or NULL for a uniform mesh on [a, b].
+ * bc: HPADI_DIRICHLET or HPADI_NEUMANN.  Host-only; EINVAL on bad sizes. */
+int hpadi_op1d_create(int n, int p, double a, double b, const double* breaks, int bc,
+                      hpadi_op1d* out);
+/* N (basis size) and Nleg = (p+1) n (Legendre coefficients per dimension). */
+int hpadi_op1d_dims(hpadi_op1d op, int* N, int* Nleg);
+/* Dense row-major host copies: K and M are N x N, T = R^T M_P is N x Nleg
+ * (Sec. 3.1).  Any pointer may be NULL to skip it.  For tests. */
+int hpadi_op1d_export(hpadi_op1d op, double* K, double* M, double* T);
+void hpadi_op1d_destroy(hpadi_op1d op);
+
+/* ---- Precomputation of Alg. 2 (host) ---------------------------------- */
+
+/* [lo, hi] containing the generalised eigenvalues of (K + omega2/2 M, M)
+ * (Alg. 2 precomputation; Sec. 5.2 lemma "Spectrum").  Lower end in closed
+ * form (pi^2/l^2 + omega2/2 Dirichlet, omega2/2 Neumann), upper end from a
+ * Lanczos iteration with a 1% margin.  ESINGULAR for Neumann with omega2 <= 0. */
+int hpadi_interval(hpadi_op1d op, double omega2, double out[2]);
+
+/* Iteration count J = ceil(log(16 gamma) log(4/tol)/pi^2) and Zolotarev shifts
+ * p_j > 0 > q_j (Alg. 2) for intervals [a,b] (of A,D) and [c,d] (of B,C) given
+ * as iv[4] = {a, b, c, d}.  If J_in > 0 it overrides the computed J.  Writes
+ * *J and, when p/q are non-NULL, up to maxJ shifts each.  EINTERVAL if the
+ * intervals overlap or are empty; EINVAL if J exceeds maxJ. */
+int hpadi_shifts(const double iv[4], double tol, int J_in, int* J, double* p, double* q, int maxJ);
+
+/* ---- Plans: factorised shift families + device workspace --------------- */
+
+/* Precomputation of Alg. 2 for A = A_Y^x, D = M^x, C = M^y, B = -A_Y^y:
+ * interval (NULL = hpadi_interval on both axes; else {a, b, c, d}), J and
+ * shifts for tol (FP64) or for the inner tolerance (MIXED), and the reverse
+ * Cholesky factorisations (Alg. 1) of K_x + (omega2/2 - q_j) M_x,
+ * K_y + (omega2/2 + p_j) M_y and of M_y, computed on the GPU in FP64 (plus
+ * FP32 copies in MIXED mode).  hip_stream: a hipStream_t or NULL.  The
+ * operators are copied; they may be destroyed afterwards.  Synchronises the
+ * stream.  ENOTSPD if a factorisation fails, ESINGULAR / EINTERVAL as above. */
+int hpadi_plan_create(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,
+                      const double* interval, void* hip_stream, hpadi_plan* out);
+int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,
+                         const double* interval, void* hip_stream, const hpadi_options* opts,
+                         hpadi_plan* out);
+/* J and (when non-NULL) the J shifts p, q and the interval of the plan's ADI
+ * family (the inner family in MIXED mode). */
+int hpadi_plan_info(hpadi_plan plan, int* J, double* p, double* q, double interval[4]);
+/* Host copy of one FP64 factor in structured form, for tests.  axis 0 = x
+ * (j-th factor of K_x + (omega2/2 - q_j) M_x), axis 1 = y (K_y + (omega2/2 +
+ * p_j) M_y); j = -1 with axis 1 is the factor of M_y.  Layout of buf
+ * (len >= 2(p-1)n + 4n + 2 n_h doubles):
+ *   invd[(p-1)n]  1 / diagonal of L at bubble (m, e), index m n + e
+ *   link[(p-1)n]  L[(m, e), (m-2, e)] at index m n + e (0 for m < 2)
+ *   cpl[4n]       L[(pi, e), hat] at index 4e + 2 pi + side, side 0 = left
+ *                 vertex of e, 1 = right vertex (0 when that hat is absent)
+ *   invd0[n_h]    1 / diagonal of the hat factor L0
+ *   link0[n_h]    L0[h, h-1] (0 for h = 0). */
+int hpadi_plan_export_factor(hpadi_plan plan, int j, int axis, double* buf, size_t len);
+
+/* G = T_x F T_y^T (Sec. 3.2): F_dev is Nleg_x x Nleg_y (ldf), G_dev is
+ * N_x x N_y (ldg), both FP64 device memory. */
+int hpadi_load(hpadi_plan plan, const double* F_dev, int ldf, double* G_dev, int ldg);
+
+/* Solve A_Y^x U M^y + M^x U A_Y^y = G (Alg. 2).  G_dev and U_dev are FP64
+ * N_x x N_y device arrays.  FP64: J ADI iterations in FP64 (relative error
+ * <= tol in the norm of the ADI lemma, Sec. 5.1).  MIXED: iterative
+ * refinement with an FP64 residual and FP32 ADI sweeps until the estimated
+ * relative error is <= tol.  stats may be NULL.  ENOCONV if the round limit
+ * is reached (U holds the last iterate).  Synchronises the stream in MIXED
+ * mode (one scalar read-back per round). */
+int hpadi_solve(hpadi_plan plan, const double* G_dev, int ldg, double* U_dev, int ldu,
+                hpadi_stats* stats);
+
+/* Y = A_Y^x U M^y + M^x U A_Y^y in FP64 (device arrays, N_x x N_y). */
+int hpadi_apply(hpadi_plan plan, const double* U_dev, int ldu, double* Y_dev, int ldy);
+
+void hpadi_plan_destroy(hpadi_plan plan);
+
+const char* hpadi_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPADI_H */

@@ -1,0 +1,1022 @@
+// Host side of hpadi: 1D operators, spectral interval, ADI shifts, plans and
+// the C ABI declared in include/hpadi.h.
+#include "hpadi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using hpadi::DimDev;
+using hpadi::FactorLayout;
+
+// ===========================================================================
+// 1D operators (Sec. 2.2-2.3, App. A).
+// ===========================================================================
+struct hpadi_op1d_s {
+    int n, p, bc, nh, N, Nleg;
+    std::vector<double> x, delta;
+
+    bool vertex_is_hat(int v) const { return bc == HPADI_DIRICHLET ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n); }
+    int hat_of_vertex(int v) const { return bc == HPADI_DIRICHLET ? v - 1 : v; }
+    int vertex_of_hat(int h) const { return bc == HPADI_DIRICHLET ? h + 1 : h; }
+    int bubble(int m, int e) const { return nh + m * n + e; }
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Bubble blocks on the reference element, scaled by delta (App. A, eq. app:1):
+double k_bub(int m) { return 4.0 / (2.0 * m + 3.0); }                                      // K (m,m) * delta
+double m_bub(int m) { return 2.0 / ((2.0 * m + 1) * (2.0 * m + 3) * (2.0 * m + 5)); }       // M (m,m) / delta
+double m_off(int m) { return -1.0 / ((2.0 * m + 3) * (2.0 * m + 5) * (2.0 * m + 7)); }      // M (m,m+2) / delta
+
+// Sparse row representation of kappa K + sigma M for one basis (host, FP64).
+struct SparseOp {
+    int N;
+    std::vector<int> ptr, col;
+    std::vector<double> val;
+};
+
+SparseOp build_op(const hpadi_op1d_s& o, double kap, double sig) {
+    std::vector<std::vector<std::pair<int, double>>> rows(o.N);
+    auto add = [&](int i, int j, double v) {
+        if (v == 0.0) return;
+        rows[i].push_back({j, v});
+    };
+    // hat-hat
+    for (int e = 0; e < o.n; ++e) {
+        const double d = o.delta[e];
+        const int vl = e, vr = e + 1;
+        const bool hl = o.vertex_is_hat(vl), hr = o.vertex_is_hat(vr);
+        const double kdg = kap / d + sig * d / 3.0, kof = -kap / d + sig * d / 6.0;
+        if (hl) add(o.hat_of_vertex(vl), o.hat_of_vertex(vl), kdg);
+        if (hr) add(o.hat_of_vertex(vr), o.hat_of_vertex(vr), kdg);
+        if (hl && hr) {
+            add(o.hat_of_vertex(vl), o.hat_of_vertex(vr), kof);
+            add(o.hat_of_vertex(vr), o.hat_of_vertex(vl), kof);
+        }
+        // hat - W_0, W_1 (mass only)
+        if (o.p >= 2) {
+            const int b0 = o.bubble(0, e);
+            if (hl) { add(o.hat_of_vertex(vl), b0, sig * d / 6.0); add(b0, o.hat_of_vertex(vl), sig * d / 6.0); }
+            if (hr) { add(o.hat_of_vertex(vr), b0, sig * d / 6.0); add(b0, o.hat_of_vertex(vr), sig * d / 6.0); }
+        }
+        if (o.p >= 3) {
+            const int b1 = o.bubble(1, e);
+            if (hl) { add(o.hat_of_vertex(vl), b1, -sig * d / 30.0); add(b1, o.hat_of_vertex(vl), -sig * d / 30.0); }
+            if (hr) { add(o.hat_of_vertex(vr), b1, sig * d / 30.0); add(b1, o.hat_of_vertex(vr), sig * d / 30.0); }
+        }
+        for (int m = 0; m + 2 <= o.p; ++m) {
+            const int b = o.bubble(m, e);
+            add(b, b, kap * k_bub(m) / d + sig * m_bub(m) * d);
+            if (m + 2 <= o.p - 2) {
+                const int b2 = o.bubble(m + 2, e);
+                add(b, b2, sig * m_off(m) * d);
+                add(b2, b, sig * m_off(m) * d);
+            }
+        }
+    }
+    SparseOp S;
+    S.N = o.N;
+    S.ptr.assign(o.N + 1, 0);
+    for (int i = 0; i < o.N; ++i) {
+        std::sort(rows[i].begin(), rows[i].end());
+        // merge duplicates (hat diagonals receive two element contributions)
+        std::vector<std::pair<int, double>> mr;
+        for (auto& kv : rows[i]) {
+            if (!mr.empty() && mr.back().first == kv.first) mr.back().second += kv.second;
+            else mr.push_back(kv);
+        }
+        rows[i] = mr;
+        S.ptr[i + 1] = S.ptr[i] + (int)mr.size();
+    }
+    for (int i = 0; i < o.N; ++i)
+        for (auto& kv : rows[i]) {
+            S.col.push_back(kv.first);
+            S.val.push_back(kv.second);
+        }
+    return S;
+}
+
+void spmv(const SparseOp& S, const double* x, double* y) {
+    for (int i = 0; i < S.N; ++i) {
+        double acc = 0.0;
+        for (int k = S.ptr[i]; k < S.ptr[i + 1]; ++k) acc += S.val[k] * x[S.col[k]];
+        y[i] = acc;
+    }
+}
+
+double entry(const SparseOp& S, int i, int j) {
+    for (int k = S.ptr[i]; k < S.ptr[i + 1]; ++k)
+        if (S.col[k] == j) return S.val[k];
+    return 0.0;
+}
+
+// Host reverse Cholesky of an arrowhead kappa K + sigma M (Alg. 1 steps, FP64),
+// in the same structured record as the device factor.  Used by the Lanczos
+// interval estimate (for M^{-1}).
+struct HostFactor {
+    FactorLayout fl;
+    std::vector<double> f;
+};
+
+bool host_factor(const hpadi_op1d_s& o, const SparseOp& S, HostFactor& H) {
+    H.fl = hpadi::make_factor_layout(o.n, o.p, o.nh);
+    H.f.assign(H.fl.size, 0.0);
+    double* F = H.f.data();
+    const int n = o.n, p = o.p;
+    for (int e = 0; e < n; ++e)
+        for (int pi = 0; pi < 2; ++pi) {
+            const int len = pi ? (p - 1) / 2 : p / 2;
+            double dup = 0.0, dhead = 1.0;
+            for (int s = len - 1; s >= 0; --s) {
+                const int m = pi + 2 * s;
+                const int b = o.bubble(m, e);
+                double a = entry(S, b, b);
+                if (s + 1 < len) {
+                    const double l = entry(S, b, o.bubble(m + 2, e)) / dup;
+                    F[H.fl.off_link + (m + 2) * n + e] = l;
+                    a -= l * l;
+                }
+                if (!(a > 0.0)) return false;
+                const double dd = std::sqrt(a);
+                F[H.fl.off_invd + m * n + e] = 1.0 / dd;
+                dup = dd;
+                if (s == 0) dhead = dd;
+            }
+            if (len > 0) {
+                const int b = o.bubble(pi, e);
+                if (o.vertex_is_hat(e)) F[H.fl.off_cpl + 4 * e + 2 * pi] = entry(S, o.hat_of_vertex(e), b) / dhead;
+                if (o.vertex_is_hat(e + 1))
+                    F[H.fl.off_cpl + 4 * e + 2 * pi + 1] = entry(S, o.hat_of_vertex(e + 1), b) / dhead;
+            }
+        }
+    const double* C = F + H.fl.off_cpl;
+    double dup = 0.0;
+    for (int h = o.nh - 1; h >= 0; --h) {
+        const int v = o.vertex_of_hat(h);
+        double a = entry(S, h, h);
+        if (v >= 1) { const int e = v - 1; a -= C[4 * e + 1] * C[4 * e + 1] + C[4 * e + 3] * C[4 * e + 3]; }
+        if (v <= n - 1) { const int e = v; a -= C[4 * e] * C[4 * e] + C[4 * e + 2] * C[4 * e + 2]; }
+        if (h + 1 < o.nh) {
+            const int e = v;
+            double b = entry(S, h, h + 1) - (C[4 * e] * C[4 * e + 1] + C[4 * e + 2] * C[4 * e + 3]);
+            const double l = b / dup;
+            F[H.fl.off_link0 + h + 1] = l;
+            a -= l * l;
+        }
+        if (!(a > 0.0)) return false;
+        const double dd = std::sqrt(a);
+        F[H.fl.off_invd0 + h] = 1.0 / dd;
+        dup = dd;
+    }
+    return true;
+}
+
+// x = S^{-1} b with the structured factor (corollary of Sec. 4), in place.
+void host_solve(const hpadi_op1d_s& o, const HostFactor& H, double* x) {
+    const double* F = H.f.data();
+    const FactorLayout& fl = H.fl;
+    const int n = o.n, p = o.p, nh = o.nh;
+    std::vector<double> hat(nh);
+    for (int h = 0; h < nh; ++h) hat[h] = x[h];
+    for (int e = 0; e < n; ++e)
+        for (int pi = 0; pi < 2; ++pi) {
+            const int len = pi ? (p - 1) / 2 : p / 2;
+            for (int s = len - 1; s >= 0; --s) {
+                const int m = pi + 2 * s;
+                double v = x[o.bubble(m, e)];
+                if (s + 1 < len) v -= F[fl.off_link + (m + 2) * n + e] * x[o.bubble(m + 2, e)];
+                x[o.bubble(m, e)] = v * F[fl.off_invd + m * n + e];
+            }
+            if (len > 0) {
+                const double y0 = x[o.bubble(pi, e)];
+                if (o.vertex_is_hat(e)) hat[o.hat_of_vertex(e)] -= F[fl.off_cpl + 4 * e + 2 * pi] * y0;
+                if (o.vertex_is_hat(e + 1)) hat[o.hat_of_vertex(e + 1)] -= F[fl.off_cpl + 4 * e + 2 * pi + 1] * y0;
+            }
+        }
+    double z = 0.0;
+    for (int h = nh - 1; h >= 0; --h) {
+        double v = hat[h];
+        if (h + 1 < nh) v -= F[fl.off_link0 + h + 1] * z;
+        z = v * F[fl.off_invd0 + h];
+        hat[h] = z;
+    }
+    double xv = 0.0;
+    for (int h = 0; h < nh; ++h) {
+        double v = hat[h];
+        if (h > 0) v -= F[fl.off_link0 + h] * xv;
+        xv = v * F[fl.off_invd0 + h];
+        hat[h] = xv;
+        x[h] = xv;
+    }
+    for (int e = 0; e < n; ++e)
+        for (int pi = 0; pi < 2; ++pi) {
+            const int len = pi ? (p - 1) / 2 : p / 2;
+            double prev = 0.0;
+            for (int s = 0; s < len; ++s) {
+                const int m = pi + 2 * s;
+                double v = x[o.bubble(m, e)];
+                if (s == 0) {
+                    if (o.vertex_is_hat(e)) v -= F[fl.off_cpl + 4 * e + 2 * pi] * hat[o.hat_of_vertex(e)];
+                    if (o.vertex_is_hat(e + 1)) v -= F[fl.off_cpl + 4 * e + 2 * pi + 1] * hat[o.hat_of_vertex(e + 1)];
+                } else {
+                    v -= F[fl.off_link + m * n + e] * prev;
+                }
+                prev = v * F[fl.off_invd + m * n + e];
+                x[o.bubble(m, e)] = prev;
+            }
+        }
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (alpha, beta) by bisection
+// on the Sturm count.
+double tridiag_max_eig(const std::vector<double>& al, const std::vector<double>& be) {
+    const int k = (int)al.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(be[i]) : 0.0);
+        lo = std::min(lo, al[i] - r);
+        hi = std::max(hi, al[i] + r);
+    }
+    auto count_above = [&](double x) {  // number of eigenvalues > x
+        int c = 0;
+        double q = 1.0;
+        for (int i = 0; i < k; ++i) {
+            const double b2 = i > 0 ? be[i - 1] * be[i - 1] : 0.0;
+            q = (al[i] - x) - (i > 0 ? b2 / q : 0.0);
+            if (q == 0.0) q = 1e-300;
+            if (q > 0) ++c;
+        }
+        return c;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::fabs(hi); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_above(mid) >= 1) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
+// Largest generalised eigenvalue of (A, M) by Lanczos in the M inner product.
+bool lanczos_lmax(const hpadi_op1d_s& o, const SparseOp& A, const SparseOp& M, const HostFactor& Mf,
+                  double* lmax) {
+    const int N = o.N;
+    std::vector<double> q(N), qprev(N, 0.0), w(N), Mq(N);
+    // deterministic start vector with components of every frequency
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    for (int i = 0; i < N; ++i) {
+        st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+        q[i] = ((st >> 11) * (1.0 / 9007199254740992.0)) - 0.5;
+    }
+    spmv(M, q.data(), Mq.data());
+    double nrm = 0.0;
+    for (int i = 0; i < N; ++i) nrm += q[i] * Mq[i];
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < N; ++i) q[i] /= nrm;
+    std::vector<double> al, be;
+    double beta = 0.0, last = 0.0;
+    int stable = 0;
+    const int kmax = std::min(600, std::max(N, 1));
+    for (int k = 0; k < kmax; ++k) {
+        spmv(A, q.data(), w.data());
+        double alpha = 0.0;
+        for (int i = 0; i < N; ++i) alpha += q[i] * w[i];
+        host_solve(o, Mf, w.data());  // w = M^{-1} A q
+        for (int i = 0; i < N; ++i) w[i] -= alpha * q[i] + beta * qprev[i];
+        spmv(M, w.data(), Mq.data());
+        double b2 = 0.0;
+        for (int i = 0; i < N; ++i) b2 += w[i] * Mq[i];
+        al.push_back(alpha);
+        const double th = tridiag_max_eig(al, be);
+        if (k > 0 && std::fabs(th - last) <= 1e-11 * std::fabs(th)) {
+            if (++stable >= 4) { last = th; break; }
+        } else {
+            stable = 0;
+        }
+        last = th;
+        if (!(b2 > 0.0)) break;
+        beta = std::sqrt(b2);
+        be.push_back(beta);
+        qprev = q;
+        for (int i = 0; i < N; ++i) q[i] = w[i] / beta;
+    }
+    *lmax = last;
+    return std::isfinite(last) && last > 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Elliptic functions and Zolotarev shifts (Alg. 2, with the cited construction).
+// ---------------------------------------------------------------------------
+double agm(double a, double b) {
+    for (int i = 0; i < 200; ++i) {
+        const double an = 0.5 * (a + b), bn = std::sqrt(a * b);
+        if (std::fabs(an - bn) <= 4e-16 * an) return 0.5 * (an + bn);
+        a = an;
+        b = bn;
+    }
+    return 0.5 * (a + b);
+}
+double K_of_kp(double kp) { return kPi / (2.0 * agm(1.0, kp)); }
+double k_of_kp(double kp) { return std::sqrt((1.0 - kp) * (1.0 + kp)); }
+
+// dn(u, k) on [0, K]: a lattice sum of hyperbolic secants with period 2K for
+// small k' (geometric convergence at ratio exp(-pi K / K')); Landen descent of
+// the amplitude with reflection about K/2 otherwise.
+double jacobi_dn(double u, double kp) {
+    const double K = K_of_kp(kp);
+    if (kp <= 0.2) {
+        const double Kp = K_of_kp(k_of_kp(kp));
+        const double c = kPi / (2.0 * Kp);
+        double s = 0.0;
+        for (int m = -8; m <= 8; ++m) {
+            const double x = c * (u - 2.0 * m * K);
+            if (std::fabs(x) < 700.0) s += 1.0 / std::cosh(x);
+        }
+        return c * s;
+    }
+    bool refl = false;
+    if (u > 0.5 * K) {
+        u = K - u;
+        refl = true;
+    }
+    double a[64], c[64];
+    double aa = 1.0, bb = kp, cc = k_of_kp(kp);
+    int N = 0;
+    a[0] = aa;
+    c[0] = cc;
+    while (std::fabs(cc) > 1e-17 * aa && N < 60) {
+        const double an = 0.5 * (aa + bb), bn = std::sqrt(aa * bb), cn = 0.5 * (aa - bb);
+        aa = an; bb = bn; cc = cn;
+        ++N;
+        a[N] = aa;
+        c[N] = cc;
+    }
+    double phi = std::ldexp(a[N] * u, N), phi1 = phi;
+    for (int i = N; i >= 1; --i) {
+        phi1 = phi;
+        phi = 0.5 * (phi + std::asin(c[i] / a[i] * std::sin(phi)));
+    }
+    const double dn = (N == 0) ? 1.0 : std::cos(phi) / std::cos(phi1 - phi);
+    return refl ? kp / dn : dn;
+}
+
+int compute_shifts(const double iv[4], double tol, int J_in, int* Jout, std::vector<double>& P,
+                   std::vector<double>& Q) {
+    const double a = iv[0], b = iv[1], c = iv[2], d = iv[3];
+    if (!(a < b && c < d) || !(d < a || b < c) || !std::isfinite(a + b + c + d)) return HPADI_EINTERVAL;
+    if (!(tol > 0.0 && tol < 1.0)) return HPADI_EINVAL;
+    const double gamma = std::fabs(c - a) * std::fabs(d - b) / (std::fabs(c - b) * std::fabs(d - a));
+    int J = J_in > 0 ? J_in : (int)std::ceil(std::log(16.0 * gamma) * std::log(4.0 / tol) / (kPi * kPi));
+    if (J < 1) J = 1;
+    const double alpha = -1.0 + 2.0 * gamma + 2.0 * std::sqrt(gamma * gamma - gamma);
+    const double kp = 1.0 / alpha;
+    const double K = K_of_kp(kp);
+    const bool sym = (c == -b && d == -a);
+    P.resize(J);
+    Q.resize(J);
+    for (int j = 1; j <= J; ++j) {
+        const double dn = jacobi_dn((2.0 * j - 1.0) * K / (2.0 * J), kp);
+        if (sym) {  // T(z) = -b / z maps -alpha, -1, 1, alpha to a, b, -b, -a
+            P[j - 1] = a / dn;
+            Q[j - 1] = -a / dn;
+        } else {  // T = psi^{-1}(phi(z)), phi(z) = cr(z; -alpha, -1, 1), psi(w) = cr(w; a, b, c)
+            auto T = [&](double z) {
+                const double ph = -2.0 * (z + alpha) / ((z - 1.0) * (alpha - 1.0));
+                return (a * (b - c) - ph * c * (b - a)) / ((b - c) - ph * (b - a));
+            };
+            P[j - 1] = T(-alpha * dn);
+            Q[j - 1] = T(alpha * dn);
+        }
+    }
+    *Jout = J;
+    return HPADI_OK;
+}
+
+int interval_of(const hpadi_op1d_s& o, double omega2, double out[2]) {
+    if (o.bc == HPADI_NEUMANN && !(omega2 > 0.0)) return HPADI_ESINGULAR;
+    if (omega2 < 0.0) return HPADI_ESINGULAR;
+    const double ell = o.x[o.n] - o.x[0];
+    const double lo = (o.bc == HPADI_DIRICHLET) ? kPi * kPi / (ell * ell) + omega2 / 2.0 : omega2 / 2.0;
+    if (o.N == 0) return HPADI_EINVAL;
+    SparseOp A = build_op(o, 1.0, omega2 / 2.0);
+    SparseOp M = build_op(o, 0.0, 1.0);
+    HostFactor Mf;
+    if (!host_factor(o, M, Mf)) return HPADI_ENOTSPD;
+    double lmax = 0.0;
+    if (!lanczos_lmax(o, A, M, Mf, &lmax)) return HPADI_EINVAL;
+    out[0] = lo;
+    out[1] = std::max(lmax * 1.01, lo * 1.0000001);
+    return HPADI_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Plan.
+// ===========================================================================
+struct DimHost {
+    hpadi_op1d_s op;
+    DimDev dev{};
+    double* buf = nullptr;  // device: delta, invdelta, mdiag, tab64
+    float* tab32 = nullptr;
+};
+
+struct hpadi_plan_s {
+    DimHost dx, dy;
+    double omega2 = 0.0, tol = 0.0;
+    int precision = HPADI_FP64;
+    hpadi_options opt{};
+    double interval[4] = {0, 0, 0, 0};
+    int J = 0;
+    std::vector<double> P, Q;
+    hipStream_t stream = nullptr;
+    bool shared = false;          // x and y use one factor family
+    FactorLayout flx{}, fly{};
+    double* facx64 = nullptr;     // J records (x: K + (w/2 - q_j) M)
+    double* facy64 = nullptr;     // J+1 records (y: K + (w/2 + p_j) M, then M)
+    float* facx32 = nullptr;
+    float* facy32 = nullptr;
+    int* status = nullptr;
+    // work arrays
+    long ldw = 0;
+    double* W64 = nullptr;
+    float* W32 = nullptr;
+    float* R32 = nullptr;
+    double* T1 = nullptr;
+    double* T2 = nullptr;
+    double* H = nullptr;          // load temporary (Nleg_x x N_y)
+    long ldh = 0;
+    double* acc = nullptr;        // device accumulators
+    double* acc_host = nullptr;   // pinned host copy
+    int lpb_col = 0, lpb_row = 0;
+};
+
+namespace {
+
+template <typename T>
+hipError_t dmalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+int make_dim(DimHost& D, const hpadi_op1d_s& o) {
+    D.op = o;
+    const int n = o.n, p = o.p, N = o.N;
+    const int ts = p + 4;
+    std::vector<double> h(2 * n + N + 3 * ts, 0.0);
+    for (int e = 0; e < n; ++e) {
+        h[e] = o.delta[e];
+        h[n + e] = 1.0 / o.delta[e];
+    }
+    SparseOp M = build_op(o, 0.0, 1.0);
+    for (int i = 0; i < N; ++i) h[2 * n + i] = entry(M, i, i);
+    double* tab = h.data() + 2 * n + N;
+    for (int m = 0; m < ts; ++m) {
+        tab[m] = k_bub(m);
+        tab[ts + m] = m_bub(m);
+        tab[2 * ts + m] = m_off(m);
+    }
+    if (dmalloc(&D.buf, h.size()) != hipSuccess) return HPADI_ENOMEM;
+    if (hipMemcpy(D.buf, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return HPADI_EHIP;
+    std::vector<float> t32(3 * ts);
+    for (int i = 0; i < 3 * ts; ++i) t32[i] = (float)tab[i];
+    if (dmalloc(&D.tab32, t32.size()) != hipSuccess) return HPADI_ENOMEM;
+    if (hipMemcpy(D.tab32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return HPADI_EHIP;
+    D.dev.n = n;
+    D.dev.p = p;
+    D.dev.nh = o.nh;
+    D.dev.N = N;
+    D.dev.Nleg = o.Nleg;
+    D.dev.bc = o.bc;
+    D.dev.delta = D.buf;
+    D.dev.invdelta = D.buf + n;
+    D.dev.mdiag = D.buf + 2 * n;
+    D.dev.tab64 = D.buf + 2 * n + N;
+    D.dev.tab32 = D.tab32;
+    D.dev.tabstride = ts;
+    return HPADI_OK;
+}
+
+void free_dim(DimHost& D) {
+    if (D.buf) hipFree(D.buf);
+    if (D.tab32) hipFree(D.tab32);
+    D.buf = nullptr;
+    D.tab32 = nullptr;
+}
+
+bool same_op(const hpadi_op1d_s& a, const hpadi_op1d_s& b) {
+    return a.n == b.n && a.p == b.p && a.bc == b.bc && a.x == b.x;
+}
+
+int factor_family(DimHost& D, const std::vector<double>& kap, const std::vector<double>& sig, FactorLayout& fl,
+                  double** f64, float** f32, bool want32, int* status, hipStream_t s) {
+    const int nf = (int)kap.size();
+    fl = hpadi::make_factor_layout(D.op.n, D.op.p, D.op.nh);
+    if (dmalloc(f64, (size_t)nf * fl.stride) != hipSuccess) return HPADI_ENOMEM;
+    if (want32 && dmalloc(f32, (size_t)nf * fl.stride) != hipSuccess) return HPADI_ENOMEM;
+    if (hipMemsetAsync(*f64, 0, (size_t)nf * fl.stride * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
+    double* ks = nullptr;
+    if (dmalloc(&ks, 2 * nf) != hipSuccess) return HPADI_ENOMEM;
+    std::vector<double> h(kap);
+    h.insert(h.end(), sig.begin(), sig.end());
+    int rc = HPADI_OK;
+    if (hipMemcpyAsync(ks, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(status, 0, nf * sizeof(int), s) != hipSuccess ||
+        hpadi::launch_factor(D.dev, nf, ks, ks + nf, *f64, want32 ? *f32 : nullptr, fl.stride, status, s) !=
+            hipSuccess) {
+        rc = HPADI_EHIP;
+    }
+    std::vector<int> st(nf, 0);
+    if (rc == HPADI_OK && (hipMemcpyAsync(st.data(), status, nf * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                           hipStreamSynchronize(s) != hipSuccess))
+        rc = HPADI_EHIP;
+    hipFree(ks);
+    if (rc != HPADI_OK) return rc;
+    for (int v : st)
+        if (v) return HPADI_ENOTSPD;
+    return HPADI_OK;
+}
+
+void plan_free(hpadi_plan_s* P) {
+    if (!P) return;
+    if (P->facy64 != P->facx64 && P->facx64) hipFree(P->facx64);
+    if (P->facy32 != P->facx32 && P->facx32) hipFree(P->facx32);
+    if (P->facy64) hipFree(P->facy64);
+    if (P->facy32) hipFree(P->facy32);
+    for (void* q : {(void*)P->status, (void*)P->W64, (void*)P->W32, (void*)P->R32, (void*)P->T1, (void*)P->T2,
+                    (void*)P->H, (void*)P->acc})
+        if (q) hipFree(q);
+    if (P->acc_host) hipHostFree(P->acc_host);
+    free_dim(P->dx);
+    free_dim(P->dy);
+    delete P;
+}
+
+int choose_lpb(int n, int p, bool fp32, bool column, int req) {
+    const int maxt = hpadi::line_pass_max_threads(p, fp32);
+    int l = req > 0 ? req : (column ? std::min(64, std::max(1, 1024 / std::max(n, 1)))
+                                    : std::max(1, 256 / std::max(n, 1)));
+    while (l > 1 && l * n > maxt) l /= 2;
+    return l;
+}
+
+// One full ADI solve (Alg. 2 solve loop) on the working arrays of type T.
+//   Gin: right-hand side (T), row-major with ld ldg.  W: work array (T), ld ldw.
+//   Final output: U (FP64) written (SOLVE, FP64 mode) or accumulated (ACCUM).
+template <typename T>
+int run_adi(hpadi_plan_s* P, const T* Gin, long ldg, T* W, double* U, long ldu, bool accumulate) {
+    const bool f32 = sizeof(T) == 4;
+    const int Nx = P->dx.op.N, Ny = P->dy.op.N;
+    const T* fx = f32 ? (const T*)P->facx32 : (const T*)P->facx64;
+    const T* fy = f32 ? (const T*)P->facy32 : (const T*)P->facy64;
+    const double half = P->omega2 / 2.0;
+    hipStream_t s = P->stream;
+    for (int j = 0; j < P->J; ++j) {
+        // row pass: x = S_y(w/2 + p_j)^{-1} R1 (rows), R2 = G - (K + (w/2 + q_j) M) x
+        hpadi::LinePass r{};
+        r.in = j == 0 ? (const void*)Gin : (const void*)W;
+        r.in_sl = j == 0 ? ldg : P->ldw;
+        r.in_sp = 1;
+        r.out = W;
+        r.out_sl = P->ldw;
+        r.out_sp = 1;
+        r.g = Gin;
+        r.g_sl = ldg;
+        r.g_sp = 1;
+        r.fac = fy + (size_t)j * P->fly.stride;
+        r.fl = P->fly;
+        r.kappa = 1.0;
+        r.tau = half + P->Q[j];
+        r.nlines = Nx;
+        if (hpadi::launch_line_pass(P->dy.dev, r, f32, f32, hpadi::MODE_PRODUCT, false, P->lpb_row, s) != hipSuccess)
+            return HPADI_EHIP;
+        // column pass: x = S_x(w/2 - q_j)^{-1} R2 (columns); R1 = G - (K + (w/2 - p_{j+1}) M) x
+        hpadi::LinePass c{};
+        c.in = W;
+        c.in_sl = 1;
+        c.in_sp = P->ldw;
+        c.out = W;
+        c.out_sl = 1;
+        c.out_sp = P->ldw;
+        c.g = Gin;
+        c.g_sl = 1;
+        c.g_sp = ldg;
+        c.fac = fx + (size_t)j * P->flx.stride;
+        c.fl = P->flx;
+        c.kappa = 1.0;
+        c.tau = (j + 1 < P->J) ? half - P->P[j + 1] : 0.0;
+        c.nlines = Ny;
+        const int mode = (j + 1 < P->J) ? hpadi::MODE_PRODUCT : hpadi::MODE_SOLVE;
+        if (hpadi::launch_line_pass(P->dx.dev, c, f32, f32, mode, true, P->lpb_col, s) != hipSuccess)
+            return HPADI_EHIP;
+    }
+    // U = W_J M_y^{-1} (row solves with the mass factor)
+    hpadi::LinePass f{};
+    f.in = W;
+    f.in_sl = P->ldw;
+    f.in_sp = 1;
+    f.out = U;
+    f.out_sl = ldu;
+    f.out_sp = 1;
+    f.fac = fy + (size_t)P->J * P->fly.stride;
+    f.fl = P->fly;
+    f.nlines = Nx;
+    f.norm_acc = accumulate ? P->acc : nullptr;
+    f.wline = P->dx.dev.mdiag;
+    const int mode = accumulate ? hpadi::MODE_ACCUM : hpadi::MODE_SOLVE;
+    if (!accumulate && f32) return HPADI_EINVAL;
+    if (hpadi::launch_line_pass(P->dy.dev, f, f32, f32, mode, false, P->lpb_row, s) != hipSuccess) return HPADI_EHIP;
+    (void)Ny;
+    return HPADI_OK;
+}
+
+// T1 = U M_y, T2 = U A_y (row operators, FP64).
+int row_products(hpadi_plan_s* P, const double* U, long ldu) {
+    hpadi::OpApply a{};
+    a.in = U;
+    a.in_sl = ldu;
+    a.in_sp = 1;
+    a.out1 = P->T1;
+    a.o1_sl = P->ldw;
+    a.o1_sp = 1;
+    a.k1 = 0.0;
+    a.t1 = 1.0;
+    a.out2 = P->T2;
+    a.o2_sl = P->ldw;
+    a.o2_sp = 1;
+    a.k2 = 1.0;
+    a.t2 = P->omega2 / 2.0;
+    a.nlines = P->dx.op.N;
+    return hpadi::launch_op_apply(P->dy.dev, a, false, P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI.
+// ===========================================================================
+extern "C" {
+
+const char* hpadi_strerror(int st) {
+    switch (st) {
+        case HPADI_OK: return "ok";
+        case HPADI_EINVAL: return "invalid argument";
+        case HPADI_ENOTSPD: return "factorisation met a non-positive pivot";
+        case HPADI_ESINGULAR: return "singular problem (Neumann with omega^2 <= 0)";
+        case HPADI_EINTERVAL: return "spectral intervals are empty or not disjoint";
+        case HPADI_ENOCONV: return "tolerance not reached";
+        case HPADI_EHIP: return "HIP runtime error";
+        case HPADI_ENOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+int hpadi_op1d_create(int n, int p, double a, double b, const double* breaks, int bc, hpadi_op1d* out) {
+    if (!out) return HPADI_EINVAL;
+    *out = nullptr;
+    if (n < 1 || p < 1 || n > 1000000 || p > 129 || (bc != HPADI_DIRICHLET && bc != HPADI_NEUMANN)) return HPADI_EINVAL;
+    hpadi_op1d_s* o = new (std::nothrow) hpadi_op1d_s;
+    if (!o) return HPADI_ENOMEM;
+    o->n = n;
+    o->p = p;
+    o->bc = bc;
+    o->x.resize(n + 1);
+    if (breaks) {
+        for (int i = 0; i <= n; ++i) o->x[i] = breaks[i];
+    } else {
+        if (!(b > a)) { delete o; return HPADI_EINVAL; }
+        for (int i = 0; i <= n; ++i) o->x[i] = a + (b - a) * (double)i / (double)n;
+        o->x[n] = b;
+    }
+    o->delta.resize(n);
+    for (int e = 0; e < n; ++e) {
+        o->delta[e] = o->x[e + 1] - o->x[e];
+        if (!(o->delta[e] > 0.0) || !std::isfinite(o->delta[e])) { delete o; return HPADI_EINVAL; }
+    }
+    o->nh = bc == HPADI_DIRICHLET ? n - 1 : n + 1;
+    o->N = o->nh + n * (p - 1);
+    o->Nleg = (p + 1) * n;
+    if (o->N < 1) { delete o; return HPADI_EINVAL; }
+    *out = o;
+    return HPADI_OK;
+}
+
+int hpadi_op1d_dims(hpadi_op1d op, int* N, int* Nleg) {
+    if (!op) return HPADI_EINVAL;
+    if (N) *N = op->N;
+    if (Nleg) *Nleg = op->Nleg;
+    return HPADI_OK;
+}
+
+int hpadi_op1d_export(hpadi_op1d op, double* K, double* M, double* T) {
+    if (!op) return HPADI_EINVAL;
+    const int N = op->N, L = op->Nleg, n = op->n;
+    auto dense = [&](const SparseOp& S, double* out) {
+        std::memset(out, 0, sizeof(double) * (size_t)N * N);
+        for (int i = 0; i < N; ++i)
+            for (int k = S.ptr[i]; k < S.ptr[i + 1]; ++k) out[(size_t)i * N + S.col[k]] = S.val[k];
+    };
+    if (K) dense(build_op(*op, 1.0, 0.0), K);
+    if (M) dense(build_op(*op, 0.0, 1.0), M);
+    if (T) {
+        std::memset(T, 0, sizeof(double) * (size_t)N * L);
+        for (int e = 0; e < n; ++e) {
+            const double d = op->delta[e];
+            if (op->vertex_is_hat(e)) {  // left vertex: (P_0 - P_1)/2 on e
+                const int h = op->hat_of_vertex(e);
+                T[(size_t)h * L + e] += d / 2.0;
+                T[(size_t)h * L + n + e] += -d / 6.0;
+            }
+            if (op->vertex_is_hat(e + 1)) {  // right vertex: (P_0 + P_1)/2 on e
+                const int h = op->hat_of_vertex(e + 1);
+                T[(size_t)h * L + e] += d / 2.0;
+                T[(size_t)h * L + n + e] += d / 6.0;
+            }
+            for (int m = 0; m + 2 <= op->p; ++m) {
+                const int b = op->bubble(m, e);
+                T[(size_t)b * L + m * n + e] = d / ((2.0 * m + 1) * (2.0 * m + 3));
+                T[(size_t)b * L + (m + 2) * n + e] = -d / ((2.0 * m + 3) * (2.0 * m + 5));
+            }
+        }
+    }
+    return HPADI_OK;
+}
+
+void hpadi_op1d_destroy(hpadi_op1d op) { delete op; }
+
+int hpadi_interval(hpadi_op1d op, double omega2, double out[2]) {
+    if (!op || !out) return HPADI_EINVAL;
+    return interval_of(*op, omega2, out);
+}
+
+int hpadi_shifts(const double iv[4], double tol, int J_in, int* J, double* p, double* q, int maxJ) {
+    if (!iv || !J) return HPADI_EINVAL;
+    std::vector<double> P, Q;
+    int Jc = 0;
+    const int rc = compute_shifts(iv, tol, J_in, &Jc, P, Q);
+    if (rc != HPADI_OK) return rc;
+    *J = Jc;
+    if (p || q) {
+        if (Jc > maxJ) return HPADI_EINVAL;
+        for (int j = 0; j < Jc; ++j) {
+            if (p) p[j] = P[j];
+            if (q) q[j] = Q[j];
+        }
+    }
+    return HPADI_OK;
+}
+
+int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,
+                         const double* interval, void* hip_stream, const hpadi_options* opts, hpadi_plan* out) {
+    if (!out) return HPADI_EINVAL;
+    *out = nullptr;
+    if (!x || !y || !(tol > 0.0 && tol < 1.0) || !std::isfinite(omega2) ||
+        (precision != HPADI_FP64 && precision != HPADI_MIXED))
+        return HPADI_EINVAL;
+    if (omega2 < 0.0 || ((x->bc == HPADI_NEUMANN || y->bc == HPADI_NEUMANN) && !(omega2 > 0.0)))
+        return HPADI_ESINGULAR;
+    if (x->p / 2 > 64 || y->p / 2 > 64) return HPADI_EINVAL;
+    hpadi_plan_s* P = new (std::nothrow) hpadi_plan_s;
+    if (!P) return HPADI_ENOMEM;
+    if (opts) P->opt = *opts;
+    if (!(P->opt.inner_tol > 0.0)) P->opt.inner_tol = 1e-5;
+    if (P->opt.max_rounds <= 0) P->opt.max_rounds = 8;
+    P->omega2 = omega2;
+    P->tol = tol;
+    P->precision = precision;
+    P->stream = (hipStream_t)hip_stream;
+    int rc;
+    // interval of Alg. 2: [a, b] for (A_Y^x, M^x), [c, d] = [-b_y, -a_y] for (-A_Y^y, M^y)
+    if (interval) {
+        for (int i = 0; i < 4; ++i) P->interval[i] = interval[i];
+    } else {
+        double ix[2], iy[2];
+        if ((rc = interval_of(*x, omega2, ix)) != HPADI_OK) { plan_free(P); return rc; }
+        if (same_op(*x, *y)) { iy[0] = ix[0]; iy[1] = ix[1]; }
+        else if ((rc = interval_of(*y, omega2, iy)) != HPADI_OK) { plan_free(P); return rc; }
+        P->interval[0] = ix[0];
+        P->interval[1] = ix[1];
+        P->interval[2] = -iy[1];
+        P->interval[3] = -iy[0];
+    }
+    const double adi_tol = precision == HPADI_FP64 ? tol : std::max(P->opt.inner_tol, tol);
+    if ((rc = compute_shifts(P->interval, adi_tol, 0, &P->J, P->P, P->Q)) != HPADI_OK) { plan_free(P); return rc; }
+    if ((rc = make_dim(P->dx, *x)) != HPADI_OK || (rc = make_dim(P->dy, *y)) != HPADI_OK) { plan_free(P); return rc; }
+    const int J = P->J;
+    if (dmalloc(&P->status, 2 * J + 2) != hipSuccess) { plan_free(P); return HPADI_ENOMEM; }
+    const bool want32 = precision == HPADI_MIXED;
+    const double half = omega2 / 2.0;
+    // y family: K_y + (w/2 + p_j) M_y for j = 1..J, then M_y
+    std::vector<double> ky(J + 1, 1.0), sy(J + 1);
+    for (int j = 0; j < J; ++j) sy[j] = half + P->P[j];
+    ky[J] = 0.0;
+    sy[J] = 1.0;
+    if ((rc = factor_family(P->dy, ky, sy, P->fly, &P->facy64, &P->facy32, want32, P->status, P->stream)) != HPADI_OK) {
+        plan_free(P);
+        return rc;
+    }
+    // x family: K_x + (w/2 - q_j) M_x; shared with y when the operators and shifts coincide
+    bool shared = same_op(*x, *y);
+    for (int j = 0; j < J && shared; ++j) shared = (-P->Q[j] == P->P[j]);
+    P->shared = shared;
+    if (shared) {
+        P->facx64 = P->facy64;
+        P->facx32 = P->facy32;
+        P->flx = P->fly;
+    } else {
+        std::vector<double> kx(J, 1.0), sx(J);
+        for (int j = 0; j < J; ++j) sx[j] = half - P->Q[j];
+        if ((rc = factor_family(P->dx, kx, sx, P->flx, &P->facx64, &P->facx32, want32, P->status + J + 1,
+                                P->stream)) != HPADI_OK) {
+            plan_free(P);
+            return rc;
+        }
+    }
+    // workspace
+    const int Nx = x->N, Ny = y->N;
+    P->ldw = ((long)Ny + 63) / 64 * 64;
+    const size_t cnt = (size_t)Nx * P->ldw;
+    bool ok = true;
+    if (precision == HPADI_FP64) {
+        ok = dmalloc(&P->W64, cnt) == hipSuccess;
+    } else {
+        ok = dmalloc(&P->W32, cnt) == hipSuccess && dmalloc(&P->R32, cnt) == hipSuccess;
+    }
+    ok = ok && dmalloc(&P->acc, 8) == hipSuccess && hipHostMalloc((void**)&P->acc_host, 8 * sizeof(double)) == hipSuccess;
+    if (!ok) { plan_free(P); return HPADI_ENOMEM; }
+    P->lpb_col = choose_lpb(x->n, x->p, want32, true, P->opt.lines_col);
+    P->lpb_row = choose_lpb(y->n, y->p, want32, false, P->opt.lines_row);
+    *out = P;
+    return HPADI_OK;
+}
+
+int hpadi_plan_create(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision, const double* interval,
+                      void* hip_stream, hpadi_plan* out) {
+    return hpadi_plan_create_ex(x, y, omega2, tol, precision, interval, hip_stream, nullptr, out);
+}
+
+int hpadi_plan_info(hpadi_plan P, int* J, double* p, double* q, double interval[4]) {
+    if (!P) return HPADI_EINVAL;
+    if (J) *J = P->J;
+    for (int j = 0; j < P->J; ++j) {
+        if (p) p[j] = P->P[j];
+        if (q) q[j] = P->Q[j];
+    }
+    if (interval)
+        for (int i = 0; i < 4; ++i) interval[i] = P->interval[i];
+    return HPADI_OK;
+}
+
+int hpadi_plan_export_factor(hpadi_plan P, int j, int axis, double* buf, size_t len) {
+    if (!P || !buf || (axis != 0 && axis != 1)) return HPADI_EINVAL;
+    const FactorLayout& fl = axis == 0 ? P->flx : P->fly;
+    const double* base = axis == 0 ? P->facx64 : P->facy64;
+    int idx = j;
+    if (j == -1) {
+        if (axis != 1) return HPADI_EINVAL;
+        idx = P->J;
+    }
+    if (idx < 0 || idx > P->J || (axis == 0 && idx >= P->J) || len < (size_t)fl.size) return HPADI_EINVAL;
+    if (hipMemcpyAsync(buf, base + (size_t)idx * fl.stride, fl.size * sizeof(double), hipMemcpyDeviceToHost,
+                       P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess)
+        return HPADI_EHIP;
+    return HPADI_OK;
+}
+
+int hpadi_load(hpadi_plan P, const double* F, int ldf, double* G, int ldg) {
+    if (!P || !F || !G || ldf < P->dy.op.Nleg || ldg < P->dy.op.N) return HPADI_EINVAL;
+    if (!P->H) {
+        P->ldh = ((long)P->dy.op.N + 63) / 64 * 64;
+        if (dmalloc(&P->H, (size_t)P->dx.op.Nleg * P->ldh) != hipSuccess) return HPADI_ENOMEM;
+    }
+    return hpadi::launch_load(P->dx.dev, P->dy.dev, F, ldf, P->H, P->ldh, G, ldg, P->stream) == hipSuccess
+               ? HPADI_OK
+               : HPADI_EHIP;
+}
+
+int hpadi_apply(hpadi_plan P, const double* U, int ldu, double* Y, int ldy) {
+    if (!P || !U || !Y || ldu < P->dy.op.N || ldy < P->dy.op.N) return HPADI_EINVAL;
+    const size_t cnt = (size_t)P->dx.op.N * P->ldw;
+    if (!P->T1 && (dmalloc(&P->T1, cnt) != hipSuccess || dmalloc(&P->T2, cnt) != hipSuccess)) return HPADI_ENOMEM;
+    int rc = row_products(P, U, ldu);
+    if (rc != HPADI_OK) return rc;
+    hpadi::Residual r{};
+    r.G = nullptr;
+    r.T1 = P->T1;
+    r.T2 = P->T2;
+    r.t_ld = P->ldw;
+    r.r64 = Y;
+    r.r64_ld = ldy;
+    r.ax_k = 1.0;
+    r.ax_t = P->omega2 / 2.0;
+    r.alpha = 0.0;
+    r.beta = 1.0;
+    r.ncols = P->dy.op.N;
+    return hpadi::launch_residual(P->dx.dev, r, P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+}
+
+int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpadi_stats* stats) {
+    if (!P || !G || !U || ldg < P->dy.op.N || ldu < P->dy.op.N) return HPADI_EINVAL;
+    hpadi_stats st{};
+    st.J = P->J;
+    for (int i = 0; i < 4; ++i) st.interval[i] = P->interval[i];
+    hipStream_t s = P->stream;
+    const int Nx = P->dx.op.N, Ny = P->dy.op.N;
+    int rc = HPADI_OK;
+    if (P->precision == HPADI_FP64) {
+        rc = run_adi<double>(P, G, ldg, P->W64, U, ldu, false);
+        st.rounds = 1;
+        st.iters = P->J;
+        st.est_rel_err = P->tol;
+    } else {
+        // Iterative refinement: U = 0; repeat { delta = ADI_fp32(r); U += delta; r = G - A U (FP64) }.
+        const size_t cnt = (size_t)Nx * P->ldw;
+        if (!P->T1 && (dmalloc(&P->T1, cnt) != hipSuccess || dmalloc(&P->T2, cnt) != hipSuccess)) return HPADI_ENOMEM;
+        if (hpadi::launch_zero_f64(U, ldu, Nx, Ny, s) != hipSuccess) return HPADI_EHIP;
+        if (hpadi::launch_convert_f64_f32(G, ldg, P->R32, P->ldw, Nx, Ny, nullptr, nullptr, nullptr, s) != hipSuccess)
+            return HPADI_EHIP;
+        double nd_prev = 0.0, est = 1.0, gnorm = 0.0;
+        const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
+        int k = 0;
+        bool done = false;
+        for (k = 1; k <= maxr && !done; ++k) {
+            if (hipMemsetAsync(P->acc, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
+            if ((rc = run_adi<float>(P, P->R32, P->ldw, P->W32, U, ldu, true)) != HPADI_OK) return rc;
+            st.iters += P->J;
+            if (P->opt.fixed_rounds <= 0) {
+                if (hipMemcpyAsync(P->acc_host, P->acc, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return HPADI_EHIP;
+                const double nd = std::sqrt(std::max(P->acc_host[0], 0.0));
+                const double nu = std::sqrt(std::max(P->acc_host[1], 0.0));
+                if (k > 1) {
+                    gnorm = std::sqrt(std::max(P->acc_host[3], 0.0));
+                    st.res_rel = gnorm > 0 ? std::sqrt(std::max(P->acc_host[2], 0.0)) / gnorm : 0.0;
+                }
+                // error after this round ~ rho ||delta_k||, rho the observed contraction per round
+                const double rho = (k == 1) ? std::max(P->opt.inner_tol, 2e-5)
+                                            : std::min(1.0, nd / std::max(nd_prev, 1e-300));
+                est = nu > 0 ? rho * nd / nu : 0.0;
+                nd_prev = nd;
+                if (!std::isfinite(est)) {
+                    st.est_rel_err = est;
+                    st.rounds = k;
+                    st.status = HPADI_ENOCONV;
+                    if (stats) *stats = st;
+                    return HPADI_ENOCONV;
+                }
+                if (est <= P->tol) {
+                    done = true;
+                    break;
+                }
+            } else if (k == maxr) {
+                break;
+            }
+            // r = G - A U in FP64, stored as the next FP32 right-hand side
+            if ((rc = row_products(P, U, ldu)) != HPADI_OK) return rc;
+            if (hipMemsetAsync(P->acc + 2, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
+            hpadi::Residual r{};
+            r.G = G;
+            r.g_ld = ldg;
+            r.T1 = P->T1;
+            r.T2 = P->T2;
+            r.t_ld = P->ldw;
+            r.r32 = P->R32;
+            r.r32_ld = P->ldw;
+            r.ax_k = 1.0;
+            r.ax_t = P->omega2 / 2.0;
+            r.alpha = 1.0;
+            r.beta = -1.0;
+            r.ncols = Ny;
+            r.norm_acc = P->acc + 2;
+            r.wcol = P->dy.dev.mdiag;
+            if (hpadi::launch_residual(P->dx.dev, r, s) != hipSuccess) return HPADI_EHIP;
+        }
+        if (k > maxr) k = maxr;
+        st.rounds = k;
+        st.est_rel_err = est;
+        if (P->opt.fixed_rounds <= 0 && !done) rc = HPADI_ENOCONV;
+    }
+    st.status = rc;
+    if (stats) *stats = st;
+    return rc;
+}
+
+void hpadi_plan_destroy(hpadi_plan P) {
+    if (P && P->stream) hipStreamSynchronize(P->stream);
+    else if (P) hipDeviceSynchronize();
+    plan_free(P);
+}
+
+}  // extern "C"

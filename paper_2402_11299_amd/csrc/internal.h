@@ -1,0 +1,114 @@
+// Internal declarations shared by the host code and the HIP kernels of hpadi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hpadi {
+
+// Device view of one 1D discretisation (Sec. 2.2: mesh, degree, boundary condition).
+struct DimDev {
+    int n, p, nh, N, Nleg, bc;  // bc: 0 Dirichlet, 1 Neumann
+    const double* delta;        // element widths, n
+    const double* invdelta;     // 1 / delta, n
+    const double* mdiag;        // diagonal of M (length N), weights of the error estimate
+    const double* tab64;        // per-degree constants, 3 * tabstride (see below)
+    const float* tab32;         // FP32 copy
+    int tabstride;              // >= p + 4
+};
+// Per-degree constant tables (m = 0 .. p-2 used), reference-element values of
+// the bubble blocks of K and M (App. A via eq. app:1):
+//   tab[0*ts + m] = 4 / (2m+3)                       K bubble diagonal * delta
+//   tab[1*ts + m] = 2 / ((2m+1)(2m+3)(2m+5))          M bubble diagonal / delta
+//   tab[2*ts + m] = -1 / ((2m+3)(2m+5)(2m+7))         M between degrees m, m+2, / delta
+
+// Offsets of one structured factor record (units: elements of the factor type).
+struct FactorLayout {
+    int nb;         // (p-1) n bubble entries
+    int off_invd;   // 1/diag of L at bubble (m, e): index m n + e
+    int off_link;   // L[(m,e),(m-2,e)]: index m n + e (0 for m < 2)
+    int off_cpl;    // coupling to hats: index 4e + 2 pi + side
+    int off_invd0;  // hat factor 1/diag, n_h
+    int off_link0;  // hat factor L0[h, h-1], n_h
+    int size;       // used length
+    int stride;     // distance between consecutive records (multiple of 64)
+};
+
+inline FactorLayout make_factor_layout(int n, int p, int nh) {
+    FactorLayout L;
+    L.nb = (p - 1) * n;
+    L.off_invd = 0;
+    L.off_link = L.nb;
+    L.off_cpl = 2 * L.nb;
+    L.off_invd0 = 2 * L.nb + 4 * n;
+    L.off_link0 = L.off_invd0 + nh;
+    L.size = L.off_link0 + nh;
+    L.stride = (L.size + 63) / 64 * 64;
+    return L;
+}
+
+// Launch helpers implemented in kernels.hip (all asynchronous on `s`).
+// Factorise nf matrices kappa[f] K + sigma[f] M of one dimension (Alg. 1).
+hipError_t launch_factor(const DimDev& d, int nf, const double* kappa_dev, const double* sigma_dev,
+                         double* fac64, float* fac32, int stride, int* status_dev, hipStream_t s);
+
+// One ADI half-sweep over all lines of an array: per line x = S^{-1} b with the
+// structured factor, then the output chosen by mode.
+enum PassMode { MODE_PRODUCT = 0, MODE_SOLVE = 1, MODE_ACCUM = 2 };
+struct LinePass {
+    const void* in;       // TW: right-hand sides b
+    long in_sl, in_sp;    // strides: line, position
+    void* out;            // TW (PRODUCT/SOLVE) or double (ACCUM)
+    long out_sl, out_sp;
+    const void* g;        // TG: G (PRODUCT only)
+    long g_sl, g_sp;
+    const void* fac;      // TW factor record
+    FactorLayout fl;
+    double kappa, tau;    // PRODUCT: out = G - (kappa K + tau M) x
+    int nlines;
+    double* norm_acc;     // ACCUM: accumulates [sum w dx^2, sum w u^2] (may be NULL)
+    const double* wline;  // ACCUM: weight per line (diag of M on the other axis)
+};
+hipError_t launch_line_pass(const DimDev& d, const LinePass& a, bool fp32, bool g_fp32, int mode,
+                            bool column, int lines_per_block, hipStream_t s);
+// Largest workgroup the line pass accepts for degree p (threads = lines_per_block * n).
+int line_pass_max_threads(int p, bool fp32);
+
+// Banded operator along lines, elementwise: out = (kappa K + tau M) x per line
+// (and optionally a second output with (kappa2, tau2)).  FP64.
+struct OpApply {
+    const double* in; long in_sl, in_sp;
+    double* out1; long o1_sl, o1_sp; double k1, t1;
+    double* out2; long o2_sl, o2_sp; double k2, t2;   // out2 may be NULL
+    int nlines;
+};
+hipError_t launch_op_apply(const DimDev& d, const OpApply& a, bool column, hipStream_t s);
+
+// r = G - (A_x T1 + M_x T2) along columns (x direction), FP64 in; writes r as FP64
+// (r64, may be NULL) and/or FP32 (r32, may be NULL); accumulates sum w r^2, sum w G^2.
+struct Residual {
+    const double* G; long g_ld;
+    const double* T1; const double* T2; long t_ld;
+    double* r64; long r64_ld;
+    float* r32; long r32_ld;
+    double ax_k, ax_t;   // A_x = ax_k K + ax_t M
+    double alpha, beta;  // r = alpha G + beta (A_x T1 + M_x T2)
+    int ncols;
+    double* norm_acc;    // [sum w r^2, sum w G^2] or NULL
+    const double* wcol;  // diag of M^y (weights along columns)
+};
+hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s);
+
+// G = T_x F T_y^T, two elementwise gather passes (Sec. 3.2).
+hipError_t launch_load(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H,
+                       long ldh, double* G, long ldg, hipStream_t s);
+
+// Convert / copy helpers.
+hipError_t launch_convert_f64_f32(const double* src, long ld_src, float* dst, long ld_dst, int rows,
+                                  int cols, double* norm_acc, const double* wr, const double* wc,
+                                  hipStream_t s);
+hipError_t launch_zero_f64(double* dst, long ld, int rows, int cols, hipStream_t s);
+
+}  // namespace hpadi

@@ -1,0 +1,296 @@
+"""ctypes binding of the hpadi C ABI (include/hpadi.h).
+
+Argument marshalling only: every step of the solver runs in libhpadi.so (host
+C++ precomputation and HIP kernels).  torch is used for device memory and the
+current stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhpadi.so")
+
+HPADI_OK, HPADI_EINVAL, HPADI_ENOTSPD, HPADI_ESINGULAR = 0, -1, -2, -3
+HPADI_EINTERVAL, HPADI_ENOCONV, HPADI_EHIP, HPADI_ENOMEM = -4, -5, -6, -7
+HPADI_DIRICHLET, HPADI_NEUMANN = 0, 1
+HPADI_FP64, HPADI_MIXED = 0, 1
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+
+
+class hpadi_stats(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_int), ("rounds", ctypes.c_int), ("iters", ctypes.c_int),
+                ("status", ctypes.c_int), ("interval", ctypes.c_double * 4),
+                ("est_rel_err", ctypes.c_double), ("res_rel", ctypes.c_double),
+                ("t_ms", ctypes.c_double * 4)]
+
+
+class hpadi_options(ctypes.Structure):
+    _fields_ = [("inner_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
+                ("lines_col", ctypes.c_int), ("lines_row", ctypes.c_int),
+                ("fixed_rounds", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+
+
+# name -> (restype, argtypes), in the order of include/hpadi.h
+SIGNATURES = {
+    "hpadi_op1d_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         _c_double_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_op1d_dims": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_int_p]),
+    "hpadi_op1d_export": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p]),
+    "hpadi_op1d_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_interval": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, _c_double_p]),
+    "hpadi_shifts": (ctypes.c_int, [_c_double_p, ctypes.c_double, ctypes.c_int, _c_int_p, _c_double_p,
+                                    _c_double_p, ctypes.c_int]),
+    "hpadi_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, _c_double_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_plan_create_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int, _c_double_p, ctypes.c_void_p,
+                                            ctypes.POINTER(hpadi_options), ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_plan_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_double_p, _c_double_p, _c_double_p]),
+    "hpadi_plan_export_factor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_double_p,
+                                                ctypes.c_size_t]),
+    "hpadi_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "hpadi_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.POINTER(hpadi_stats)]),
+    "hpadi_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "hpadi_plan_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libhpadi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2402_11299_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class HpadiError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().hpadi_strerror(status).decode()
+        super().__init__(f"{where}: {msg} ({status})")
+
+
+def check(status: int, where: str) -> None:
+    if status != HPADI_OK:
+        raise HpadiError(status, where)
+
+
+def _dptr(arr):
+    import numpy as np
+    assert arr.dtype == np.float64 and arr.flags["C_CONTIGUOUS"]
+    return arr.ctypes.data_as(_c_double_p)
+
+
+# --------------------------------------------------------------------------
+# Thin wrappers with the C names.
+# --------------------------------------------------------------------------
+
+def hpadi_op1d_create(n, p, a=0.0, b=1.0, breaks=None, bc=HPADI_DIRICHLET):
+    import numpy as np
+    h = ctypes.c_void_p()
+    br = None
+    if breaks is not None:
+        br = np.ascontiguousarray(breaks, dtype=np.float64)
+    check(lib().hpadi_op1d_create(int(n), int(p), float(a), float(b), _dptr(br) if br is not None else None,
+                                  int(bc), ctypes.byref(h)), "hpadi_op1d_create")
+    return h
+
+
+def hpadi_op1d_dims(op):
+    N, L = ctypes.c_int(), ctypes.c_int()
+    check(lib().hpadi_op1d_dims(op, ctypes.byref(N), ctypes.byref(L)), "hpadi_op1d_dims")
+    return N.value, L.value
+
+
+def hpadi_op1d_export(op):
+    import numpy as np
+    N, L = hpadi_op1d_dims(op)
+    K, M, T = np.zeros((N, N)), np.zeros((N, N)), np.zeros((N, L))
+    check(lib().hpadi_op1d_export(op, _dptr(K), _dptr(M), _dptr(T)), "hpadi_op1d_export")
+    return K, M, T
+
+
+def hpadi_op1d_destroy(op):
+    lib().hpadi_op1d_destroy(op)
+
+
+def hpadi_interval(op, omega2):
+    out = (ctypes.c_double * 2)()
+    check(lib().hpadi_interval(op, float(omega2), out), "hpadi_interval")
+    return out[0], out[1]
+
+
+def hpadi_shifts(iv, tol, J=0, maxJ=512):
+    iv_c = (ctypes.c_double * 4)(*[float(v) for v in iv])
+    Jc = ctypes.c_int()
+    p = (ctypes.c_double * maxJ)()
+    q = (ctypes.c_double * maxJ)()
+    check(lib().hpadi_shifts(iv_c, float(tol), int(J), ctypes.byref(Jc), p, q, maxJ), "hpadi_shifts")
+    return Jc.value, list(p[:Jc.value]), list(q[:Jc.value])
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def hpadi_plan_create(x, y, omega2, tol, precision=HPADI_FP64, interval=None, stream=None, options=None):
+    h = ctypes.c_void_p()
+    iv = (ctypes.c_double * 4)(*[float(v) for v in interval]) if interval is not None else None
+    if options is None:
+        st = lib().hpadi_plan_create(x, y, float(omega2), float(tol), int(precision), iv,
+                                     _stream_handle(stream), ctypes.byref(h))
+    else:
+        st = lib().hpadi_plan_create_ex(x, y, float(omega2), float(tol), int(precision), iv,
+                                        _stream_handle(stream), ctypes.byref(options), ctypes.byref(h))
+    check(st, "hpadi_plan_create")
+    return h
+
+
+def hpadi_plan_info(plan, maxJ=512):
+    J = ctypes.c_int()
+    p = (ctypes.c_double * maxJ)()
+    q = (ctypes.c_double * maxJ)()
+    iv = (ctypes.c_double * 4)()
+    check(lib().hpadi_plan_info(plan, ctypes.byref(J), None, None, iv), "hpadi_plan_info")
+    if J.value > maxJ:
+        raise ValueError("too many shifts")
+    check(lib().hpadi_plan_info(plan, ctypes.byref(J), p, q, iv), "hpadi_plan_info")
+    return J.value, list(p[:J.value]), list(q[:J.value]), list(iv)
+
+
+def hpadi_plan_export_factor(plan, j, axis, length):
+    import numpy as np
+    buf = np.zeros(length)
+    check(lib().hpadi_plan_export_factor(plan, int(j), int(axis), _dptr(buf), buf.size),
+          "hpadi_plan_export_factor")
+    return buf
+
+
+def _tptr(t, dtype_name="float64"):
+    import torch
+    if not t.is_cuda or t.dtype != getattr(torch, dtype_name) or t.stride(1) != 1:
+        raise ValueError("expected a row-major CUDA float64 tensor")
+    return ctypes.c_void_p(t.data_ptr()), int(t.stride(0))
+
+
+def hpadi_load(plan, F, G):
+    fp, ldf = _tptr(F)
+    gp, ldg = _tptr(G)
+    check(lib().hpadi_load(plan, fp, ldf, gp, ldg), "hpadi_load")
+
+
+def hpadi_solve(plan, G, U, raise_on_noconv=True):
+    gp, ldg = _tptr(G)
+    up, ldu = _tptr(U)
+    st = hpadi_stats()
+    rc = lib().hpadi_solve(plan, gp, ldg, up, ldu, ctypes.byref(st))
+    if rc != HPADI_OK and (raise_on_noconv or rc != HPADI_ENOCONV):
+        raise HpadiError(rc, "hpadi_solve")
+    return st
+
+
+def hpadi_apply(plan, U, Y):
+    up, ldu = _tptr(U)
+    yp, ldy = _tptr(Y)
+    check(lib().hpadi_apply(plan, up, ldu, yp, ldy), "hpadi_apply")
+
+
+def hpadi_plan_destroy(plan):
+    lib().hpadi_plan_destroy(plan)
+
+
+def hpadi_strerror(status):
+    return lib().hpadi_strerror(int(status)).decode()
+
+
+# --------------------------------------------------------------------------
+# Small object layer.
+# --------------------------------------------------------------------------
+
+class Op1D:
+    """A 1D discretisation handle (mesh, degree, BC)."""
+
+    def __init__(self, n, p, a=0.0, b=1.0, bc="dirichlet", breaks=None):
+        self.n, self.p, self.a, self.b = n, p, a, b
+        self.bc = bc
+        code = HPADI_DIRICHLET if bc == "dirichlet" else HPADI_NEUMANN
+        self.handle = hpadi_op1d_create(n, p, a, b, breaks, code)
+        self.N, self.Nleg = hpadi_op1d_dims(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            hpadi_op1d_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Factorised ADI plan on the GPU (Alg. 2 precomputation)."""
+
+    def __init__(self, x: Op1D, y: Op1D, omega2, tol, precision="fp64", interval=None, stream=None,
+                 options=None):
+        self.x, self.y = x, y
+        self.precision = precision
+        code = HPADI_FP64 if precision == "fp64" else HPADI_MIXED
+        self.handle = hpadi_plan_create(x.handle, y.handle, omega2, tol, code, interval, stream, options)
+        self.J, self.p, self.q, self.interval = hpadi_plan_info(self.handle)
+
+    def load(self, F):
+        import torch
+        if tuple(F.shape) != (self.x.Nleg, self.y.Nleg):
+            raise ValueError(f"F must be {self.x.Nleg} x {self.y.Nleg}")
+        G = torch.empty((self.x.N, self.y.N), dtype=torch.float64, device=F.device)
+        hpadi_load(self.handle, F, G)
+        return G
+
+    def solve(self, G, U=None, raise_on_noconv=True):
+        import torch
+        if tuple(G.shape) != (self.x.N, self.y.N) or (U is not None and tuple(U.shape) != tuple(G.shape)):
+            raise ValueError(f"G and U must be {self.x.N} x {self.y.N}")
+        if U is None:
+            U = torch.empty((self.x.N, self.y.N), dtype=torch.float64, device=G.device)
+        st = hpadi_solve(self.handle, G, U, raise_on_noconv)
+        return U, st
+
+    def apply(self, U):
+        import torch
+        if tuple(U.shape) != (self.x.N, self.y.N):
+            raise ValueError(f"U must be {self.x.N} x {self.y.N}")
+        Y = torch.empty_like(U)
+        hpadi_apply(self.handle, U, Y)
+        return Y
+
+    def close(self):
+        if self.handle is not None:
+            hpadi_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,96 @@
+"""CPU tests of the C-ABI library: symbols, host-side assembly, interval and shifts
+against the oracle (no GPU compute)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis as obasis
+from oracle import shifts as oshifts
+from oracle import spectrum as ospectrum
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2402_11299_amd import hpadi
+    if not os.path.exists(hpadi.LIB_PATH):
+        pytest.skip("libhpadi.so not built")
+    hpadi.lib()
+    return hpadi
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "hpadi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpadi_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol(hp):
+    names = declared_symbols()
+    assert len(names) >= 15
+    L = hp.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(hp.SIGNATURES), "binding and header disagree"
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+@pytest.mark.parametrize("n,p,breaks", [(1, 2, None), (4, 8, None), (3, 7, [0.0, 0.2, 0.9, 1.3]),
+                                        (5, 1, None), (2, 13, [-1.0, 0.5, 2.0])])
+def test_host_operators_match_oracle(hp, bc, n, p, breaks):
+    if bc == "dirichlet" and n == 1 and p == 1:
+        pytest.skip("empty space")
+    a, b = (breaks[0], breaks[-1]) if breaks else (0.0, 1.0)
+    op = hp.Op1D(n, p, a, b, bc, breaks)
+    K, M, T = hp.hpadi_op1d_export(op.handle)
+    ref = obasis.assemble(obasis.make_basis(n, p, a, b, bc, breaks))
+    assert np.abs(K - ref.K.toarray()).max() <= 1e-13 * np.abs(K).max()
+    assert np.abs(M - ref.M.toarray()).max() <= 1e-15
+    assert np.abs(T - ref.T.toarray()).max() <= 1e-15
+
+
+@pytest.mark.parametrize("iv", [(9.8696, 5.031e4, -5.031e4, -9.8696), (0.5, 3.056e10, -3.056e10, -0.5),
+                                (9.87, 5.0e4, -2.6e3, -2.47), (0.005, 2.093e9, -1.8e9, -509.87),
+                                (1.0, 3.0, -2.0, -0.5)])
+@pytest.mark.parametrize("tol", [1e-4, 1e-10, 1e-12])
+def test_host_shifts_match_oracle(hp, iv, tol):
+    J, p, q = hp.hpadi_shifts(iv, tol)
+    Jo, po, qo = oshifts.adi_shifts(*iv, tol)
+    assert J == Jo
+    assert np.allclose(p, po, rtol=1e-12)
+    assert np.allclose(q, qo, rtol=1e-12)
+
+
+@pytest.mark.parametrize("bc,w2", [("dirichlet", 0.0), ("neumann", 1.0), ("dirichlet", 10.0),
+                                   ("neumann", 1e-2)])
+@pytest.mark.parametrize("n,p", [(4, 8), (8, 16), (2, 40)])
+def test_host_interval_contains_spectrum(hp, bc, w2, n, p):
+    op = hp.Op1D(n, p, 0.0, 1.0, bc)
+    lo, hi = hp.hpadi_interval(op.handle, w2)
+    ops = obasis.assemble(obasis.make_basis(n, p, 0.0, 1.0, bc))
+    lmin, lmax = ospectrum.extreme_eigenvalues(ops, w2)
+    assert lo <= lmin * (1 + 1e-9)
+    assert lmax <= hi <= 1.02 * lmax
+
+
+def test_error_codes(hp):
+    with pytest.raises(hp.HpadiError) as ei:
+        hp.hpadi_op1d_create(0, 4)
+    assert ei.value.status == hp.HPADI_EINVAL
+    op = hp.Op1D(3, 4, 0, 1, "neumann")
+    with pytest.raises(hp.HpadiError) as ei:
+        hp.hpadi_interval(op.handle, 0.0)
+    assert ei.value.status == hp.HPADI_ESINGULAR
+    with pytest.raises(hp.HpadiError) as ei:
+        hp.hpadi_shifts((1.0, 5.0, 2.0, 8.0), 1e-6)      # overlapping intervals
+    assert ei.value.status == hp.HPADI_EINTERVAL
+    with pytest.raises(hp.HpadiError) as ei:
+        hp.hpadi_shifts((1.0, 5.0, -5.0, -1.0), 0.0)
+    assert ei.value.status == hp.HPADI_EINVAL
+    with pytest.raises(hp.HpadiError) as ei:
+        hp.hpadi_op1d_create(3, 4, 0.0, 1.0, breaks=[0.0, 0.5, 0.4, 1.0])
+    assert ei.value.status == hp.HPADI_EINVAL
+    assert "tolerance" in hp.hpadi_strerror(hp.HPADI_ENOCONV)
