@@ -1,0 +1,221 @@
+"""Benchmark of the ADI hp-FEM screened-Poisson solve on one MI355X.
+
+A step is one whole solve, G resident in HBM -> U resident in HBM: the
+mixed-precision solver (FP32 ADI sweeps, FP64 residual and refinement) on
+-Laplace(u) = f, zero Dirichlet, [0,1]^2, n = p = 64 (N = 4095 per dimension),
+relative error 1e-10.  Reported beside it: FP64 ADI on the same problem and GPU,
+the Neumann variant (omega^2 = 1, N = 4097), the roofline of the dominant
+kernel (HIP events around every half-sweep launch on the solver's stream), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DOF/s of ADI hp-FEM Poisson at rel err 1e-10: mixed vs FP64; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_problem(hp, torch, cfg):
+    import workloads
+    x = hp.Op1D(cfg.nx, cfg.px, cfg.ax, cfg.bx, cfg.bc)
+    y = hp.Op1D(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc)
+    F = torch.from_numpy(workloads.legendre_rhs(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.seed)).cuda()
+    return x, y, F
+
+
+def time_solves(torch, plan, G, U, steps, warmup):
+    for _ in range(warmup):
+        plan.solve(G, U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = None
+    for _ in range(steps):
+        _, st = plan.solve(G, U)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, st
+
+
+def oracle_error_roundtrip(hp, torch, cfg, plan_mixed):
+    """Relative L2 error of a full-size mixed solve whose exact answer is known:
+    U0 is drawn, G0 = A U0 is formed by the FP64 oracle, the GPU solves G0."""
+    import numpy as np
+    from oracle import adi as oadi
+    from oracle import basis as obasis
+    ox = obasis.assemble(obasis.make_basis(cfg.nx, cfg.px, cfg.ax, cfg.bx, cfg.bc))
+    oy = obasis.assemble(obasis.make_basis(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc))
+    rng = np.random.default_rng(cfg.seed + 1000)
+    U0 = rng.standard_normal((ox.basis.N, oy.basis.N))
+    G0 = oadi.apply_operator(ox, oy, cfg.omega2, U0)
+    U, st = plan_mixed.solve(torch.from_numpy(G0).cuda())
+    return oadi.rel_l2_error(U.cpu().numpy(), U0, ox, oy), st
+
+
+def cpu_baseline(cfg, interval, j_full, j_sample=1):
+    """The FP64 oracle (Alg. 2 in NumPy) on the same problem, j_sample ADI
+    iterations timed and scaled to the j_full iterations of an FP64 solve."""
+    import workloads
+    from oracle import adi as oadi
+    from oracle import basis as obasis
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    ox = obasis.assemble(obasis.make_basis(cfg.nx, cfg.px, cfg.ax, cfg.bx, cfg.bc))
+    oy = obasis.assemble(obasis.make_basis(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc))
+    F = workloads.legendre_rhs(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.seed)
+    G = oadi.load(ox, oy, F)
+    plan = oadi.ADIPlan(ox, oy, cfg.omega2, cfg.tol, interval=interval, J=j_sample)
+    t0 = time.perf_counter()
+    plan.solve(G)
+    t = time.perf_counter() - t0
+    N2 = ox.basis.N * oy.basis.N
+    t_full = t / j_sample * j_full
+    return {"value": N2 / t_full, "unit": "DOF/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle FP64 Alg. 2 solve at N={ox.basis.N}x{oy.basis.N}: {j_sample} of "
+                       f"{j_full} iterations (plus the final mass solve) timed ({t:.1f} s), "
+                       f"scaled to {j_full} iterations; BLAS threads={cores}, os.cpu_count={os.cpu_count()}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--only-mixed", action="store_true", help="time only the headline solve (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X; "
+              "a multi-GPU run is not part of this build (see DESIGN.md for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2402_11299_amd import hpadi as hp
+    hp.lib()
+    torch.cuda.init()
+    cfgD = workloads.CFG_MIXED_4K_D
+    cfgN = workloads.CFG_MIXED_4K_N
+
+    out = {}
+    # ---- headline: mixed precision, Dirichlet, N = 4095
+    x, y, F = make_problem(hp, torch, cfgD)
+    t0 = time.perf_counter()
+    pm = hp.Plan(x, y, cfgD.omega2, cfgD.tol, "mixed")
+    t_plan_mixed = time.perf_counter() - t0
+    G = pm.load(F)
+    U = torch.empty_like(G)
+    log(f"mixed plan: J_inner={pm.J} interval={pm.interval} plan {t_plan_mixed*1e3:.1f} ms")
+    hp.hpadi_plan_timing(pm.handle, True)
+    t_mixed, st_mixed = time_solves(torch, pm, G, U, args.steps, args.warmup)
+    ms, by, ct = hp.hpadi_plan_timing_read(pm.handle)
+    hp.hpadi_plan_timing(pm.handle, False)
+    N2 = x.N * y.N
+    log(f"mixed: {t_mixed*1e3:.3f} ms/solve, rounds={st_mixed.rounds}, est={st_mixed.est_rel_err:.2e}")
+    kinds = ["column_sweep", "row_sweep", "mass_solve"]
+    per_kernel = {}
+    for k in range(3):
+        if ct[k]:
+            per_kernel[kinds[k]] = {"launches": ct[k], "avg_us": ms[k] / ct[k] * 1e3,
+                                    "GBps": by[k] / (ms[k] * 1e-3) / 1e9}
+    dom = max(range(2), key=lambda k: ms[k])
+    launches_per_step = ct[dom] / (args.steps + args.warmup)
+    roof = {"bound": "hbm", "kernel": f"line_pass_kernel<float> ({kinds[dom]})",
+            "achieved": by[dom] / (ms[dom] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "traffic": None,
+            "bytes_per_launch": by[dom] / ct[dom], "avg_launch_us": ms[dom] / ct[dom] * 1e3,
+            "launches_per_step": launches_per_step}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    sweep_ms = sum(ms) / (args.steps + args.warmup)
+    roof["sweeps_share_of_step"] = sweep_ms / (t_mixed * 1e3)
+
+    err_rt = None
+    if not args.no_oracle_check:
+        err_rt, st_rt = oracle_error_roundtrip(hp, torch, cfgD, pm)
+        log(f"round-trip error vs oracle: {err_rt:.3e} (rounds {st_rt.rounds})")
+
+    if not args.only_mixed:
+        # ---- FP64 ADI on the same problem
+        pf = hp.Plan(x, y, cfgD.omega2, cfgD.tol, "fp64")
+        Uf = torch.empty_like(G)
+        t_fp64, _ = time_solves(torch, pf, G, Uf, max(2, args.steps // 2), 1)
+        d = (U - Uf)
+        rel_mixed_vs_fp64 = float(torch.linalg.norm(d) / torch.linalg.norm(Uf))
+        log(f"fp64: J={pf.J} {t_fp64*1e3:.3f} ms/solve; |U_mixed - U_fp64|/|U_fp64| = {rel_mixed_vs_fp64:.2e}")
+        out["fp64_dof_per_s"] = N2 / t_fp64
+        out["fp64_ms_per_solve"] = t_fp64 * 1e3
+        out["fp64_J"] = pf.J
+        out["mixed_over_fp64"] = t_fp64 / t_mixed
+        out["coef_rel_diff_mixed_vs_fp64"] = rel_mixed_vs_fp64
+        pf.close()
+        # ---- Neumann, omega^2 = 1, N = 4097 (separate runs)
+        xn, yn, Fn = make_problem(hp, torch, cfgN)
+        pmn = hp.Plan(xn, yn, cfgN.omega2, cfgN.tol, "mixed")
+        Gn = pmn.load(Fn)
+        Un = torch.empty_like(Gn)
+        t_mn, st_mn = time_solves(torch, pmn, Gn, Un, max(2, args.steps // 2), 1)
+        pfn = hp.Plan(xn, yn, cfgN.omega2, cfgN.tol, "fp64")
+        Ufn = torch.empty_like(Gn)
+        t_fn, _ = time_solves(torch, pfn, Gn, Ufn, max(2, args.steps // 2), 1)
+        N2n = xn.N * yn.N
+        log(f"neumann: mixed {t_mn*1e3:.3f} ms ({st_mn.rounds} rounds), fp64 {t_fn*1e3:.3f} ms (J={pfn.J})")
+        out["neumann"] = {"N": xn.N, "omega2": cfgN.omega2, "mixed_dof_per_s": N2n / t_mn,
+                          "fp64_dof_per_s": N2n / t_fn, "mixed_rounds": st_mn.rounds,
+                          "mixed_J_inner": pmn.J, "fp64_J": pfn.J,
+                          "coef_rel_diff_mixed_vs_fp64": float(torch.linalg.norm(Un - Ufn) / torch.linalg.norm(Ufn))}
+        pmn.close()
+        pfn.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        j_full = hp.hpadi_shifts(pm.interval, cfgD.tol)[0]
+        cpu = cpu_baseline(cfgD, pm.interval, j_full)
+        log(f"cpu baseline: {cpu['value']:.3e} DOF/s")
+
+    line = {
+        "metric": METRIC,
+        "value": N2 / t_mixed,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 sweeps + f64 residual/refinement",
+        "data": "synthetic",
+        "config": {"workload": "poisson_n64_p64_dirichlet: -Laplace u = f on [0,1]^2, zero Dirichlet, "
+                               "n=p=64 (N=4095 per dim), random Legendre f (seed 2), mixed precision, rel err 1e-10",
+                   "N": x.N, "n": cfgD.nx, "p": cfgD.px, "tol": cfgD.tol, "J_inner": pm.J,
+                   "rounds": st_mixed.rounds, "est_rel_err": st_mixed.est_rel_err,
+                   "rel_err_vs_oracle_roundtrip": err_rt, "plan_ms": t_plan_mixed * 1e3},
+        "roofline": roof,
+        "kernels": per_kernel,
+        "cpu_baseline": cpu,
+    }
+    line.update(out)
+    print(json.dumps(line), flush=True)
+    pm.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -132,7 +132,7 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
 int hpadi_plan_info(hpadi_plan plan, int* J, double* p, double* q, double interval[4]);
 /* Host copy of one FP64 factor in structured form, for tests.  axis 0 = x
  * (j-th factor of K_x + (omega2/2 - q_j) M_x), axis 1 = y (K_y + (omega2/2 +
- * p_j) M_y); j = -1 with axis 1 is the factor of M_y.  Layout of buf
+ * p_j) M_y); j = -1 is the factor of the mass matrix of that axis.  Layout of buf
  * (len >= 2(p-1)n + 4n + 2 n_h doubles):
  *   invd[(p-1)n]  1 / diagonal of L at bubble (m, e), index m n + e
  *   link[(p-1)n]  L[(m, e), (m-2, e)] at index m n + e (0 for m < 2)
@@ -160,6 +160,21 @@ int hpadi_solve(hpadi_plan plan, const double* G_dev, int ldg, double* U_dev, in
 int hpadi_apply(hpadi_plan plan, const double* U_dev, int ldu, double* Y_dev, int ldy);
 
 void hpadi_plan_destroy(hpadi_plan plan);
+
+/* ---- Measurement ------------------------------------------------------- */
+
+/* Kernel timing for roofline measurement: while enabled, HIP events are
+ * recorded on the plan's stream around every half-sweep launch.  enable = 1
+ * clears the totals and starts recording, 0 stops.  At most 65536 launches are
+ * recorded per enable; later launches run untimed. */
+int hpadi_plan_timing(hpadi_plan plan, int enable);
+/* Totals since the last enable, by kind: 0 = column half-sweeps of the ADI
+ * loop, 1 = row half-sweeps, 2 = the transforms into and out of the
+ * mass-balanced coordinates.  ms[k]: summed kernel durations; bytes[k]: summed
+ * algorithmic HBM bytes of those launches (every array entry read or written
+ * once: input, G~ and output of a fused sweep); count[k]: launches.  Any
+ * pointer may be NULL.  Synchronises the stream. */
+int hpadi_plan_timing_read(hpadi_plan plan, double ms[3], double bytes[3], int count[3]);
 
 const char* hpadi_strerror(int status);
 

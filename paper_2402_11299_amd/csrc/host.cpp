@@ -428,6 +428,9 @@ struct DimHost {
     DimDev dev{};
     double* buf = nullptr;  // device: delta, invdelta, mdiag, tab64
     float* tab32 = nullptr;
+    int hpad = 0;           // hats padded to a multiple of 8 (internal layout)
+    int Npad = 0;           // internal length: hpad + (p-1) n
+    bool uniform = false;   // all elements of equal width and n % 8 == 0 (per-degree coefficient fast path)
 };
 
 struct hpadi_plan_s {
@@ -441,23 +444,31 @@ struct hpadi_plan_s {
     hipStream_t stream = nullptr;
     bool shared = false;          // x and y use one factor family
     FactorLayout flx{}, fly{};
-    double* facx64 = nullptr;     // J records (x: K + (w/2 - q_j) M)
-    double* facy64 = nullptr;     // J+1 records (y: K + (w/2 + p_j) M, then M)
-    float* facx32 = nullptr;
-    float* facy32 = nullptr;
+    double* facx64 = nullptr;     // J+1 records: K_x + (w/2 - q_j) M_x, then M_x
+    double* facy64 = nullptr;     // J+1 records: K_y + (w/2 + p_j) M_y, then M_y
+    double* coefx = nullptr;      // uniform meshes: (J+1) (p_x-1) 8 per-degree coefficient records
+    double* coefy = nullptr;
     int* status = nullptr;
-    // work arrays
+    // work arrays in the internal panel layout
+    hpadi::Layout lint{};
+    size_t nint = 0;              // elements per internal array
+    void* Wk = nullptr;           // balanced iterate (TS)
+    void* Gt = nullptr;           // balanced right-hand side G~ (TS)
+    double* T64 = nullptr;        // transform temporary (FP64, internal layout)
+    // FP64 row-major work (mixed refinement, apply)
     long ldw = 0;
-    double* W64 = nullptr;
-    float* W32 = nullptr;
-    float* R32 = nullptr;
     double* T1 = nullptr;
     double* T2 = nullptr;
+    double* R64 = nullptr;
     double* H = nullptr;          // load temporary (Nleg_x x N_y)
     long ldh = 0;
     double* acc = nullptr;        // device accumulators
     double* acc_host = nullptr;   // pinned host copy
-    int lpb_col = 0, lpb_row = 0;
+    // measurement
+    bool timing = false;
+    struct Rec { hipEvent_t a, b; int kind; double bytes; };
+    std::vector<Rec> recs;        // event pool; the first nrec are in use
+    size_t nrec = 0;
 };
 
 namespace {
@@ -504,6 +515,10 @@ int make_dim(DimHost& D, const hpadi_op1d_s& o) {
     D.dev.tab64 = D.buf + 2 * n + N;
     D.dev.tab32 = D.tab32;
     D.dev.tabstride = ts;
+    D.hpad = (o.nh + 7) / 8 * 8;
+    D.Npad = D.hpad + (p - 1) * n;
+    D.uniform = n % 8 == 0;
+    for (int e = 1; e < n && D.uniform; ++e) D.uniform = o.delta[e] == o.delta[0];
     return HPADI_OK;
 }
 
@@ -519,11 +534,10 @@ bool same_op(const hpadi_op1d_s& a, const hpadi_op1d_s& b) {
 }
 
 int factor_family(DimHost& D, const std::vector<double>& kap, const std::vector<double>& sig, FactorLayout& fl,
-                  double** f64, float** f32, bool want32, int* status, hipStream_t s) {
+                  double** f64, int* status, hipStream_t s) {
     const int nf = (int)kap.size();
     fl = hpadi::make_factor_layout(D.op.n, D.op.p, D.op.nh);
     if (dmalloc(f64, (size_t)nf * fl.stride) != hipSuccess) return HPADI_ENOMEM;
-    if (want32 && dmalloc(f32, (size_t)nf * fl.stride) != hipSuccess) return HPADI_ENOMEM;
     if (hipMemsetAsync(*f64, 0, (size_t)nf * fl.stride * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
     double* ks = nullptr;
     if (dmalloc(&ks, 2 * nf) != hipSuccess) return HPADI_ENOMEM;
@@ -532,8 +546,7 @@ int factor_family(DimHost& D, const std::vector<double>& kap, const std::vector<
     int rc = HPADI_OK;
     if (hipMemcpyAsync(ks, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemsetAsync(status, 0, nf * sizeof(int), s) != hipSuccess ||
-        hpadi::launch_factor(D.dev, nf, ks, ks + nf, *f64, want32 ? *f32 : nullptr, fl.stride, status, s) !=
-            hipSuccess) {
+        hpadi::launch_factor(D.dev, nf, ks, ks + nf, *f64, nullptr, fl.stride, status, s) != hipSuccess) {
         rc = HPADI_EHIP;
     }
     std::vector<int> st(nf, 0);
@@ -550,94 +563,131 @@ int factor_family(DimHost& D, const std::vector<double>& kap, const std::vector<
 void plan_free(hpadi_plan_s* P) {
     if (!P) return;
     if (P->facy64 != P->facx64 && P->facx64) hipFree(P->facx64);
-    if (P->facy32 != P->facx32 && P->facx32) hipFree(P->facx32);
     if (P->facy64) hipFree(P->facy64);
-    if (P->facy32) hipFree(P->facy32);
-    for (void* q : {(void*)P->status, (void*)P->W64, (void*)P->W32, (void*)P->R32, (void*)P->T1, (void*)P->T2,
+    if (P->coefy != P->coefx && P->coefx) hipFree(P->coefx);
+    if (P->coefy) hipFree(P->coefy);
+    for (void* q : {(void*)P->status, P->Wk, P->Gt, (void*)P->T64, (void*)P->T1, (void*)P->T2, (void*)P->R64,
                     (void*)P->H, (void*)P->acc})
         if (q) hipFree(q);
     if (P->acc_host) hipHostFree(P->acc_host);
+    for (auto& r : P->recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
     free_dim(P->dx);
     free_dim(P->dy);
     delete P;
 }
 
-int choose_lpb(int n, int p, bool fp32, bool column, int req) {
-    const int maxt = hpadi::line_pass_max_threads(p, fp32);
-    int l = req > 0 ? req : (column ? std::min(64, std::max(1, 1024 / std::max(n, 1)))
-                                    : std::max(1, 256 / std::max(n, 1)));
-    while (l > 1 && l * n > maxt) l /= 2;
-    return l;
+hpadi::Layout user_layout(const hpadi_plan_s* P, long ld) {
+    hpadi::Layout L{};
+    L.ld = ld;
+    L.panel = 0;
+    L.nhr = P->dx.op.nh;
+    L.nhc = P->dy.op.nh;
+    return L;
 }
 
-// One full ADI solve (Alg. 2 solve loop) on the working arrays of type T.
-//   Gin: right-hand side (T), row-major with ld ldg.  W: work array (T), ld ldw.
-//   Final output: U (FP64) written (SOLVE, FP64 mode) or accumulated (ACCUM).
-template <typename T>
-int run_adi(hpadi_plan_s* P, const T* Gin, long ldg, T* W, double* U, long ldu, bool accumulate) {
-    const bool f32 = sizeof(T) == 4;
-    const int Nx = P->dx.op.N, Ny = P->dy.op.N;
-    const T* fx = f32 ? (const T*)P->facx32 : (const T*)P->facx64;
-    const T* fy = f32 ? (const T*)P->facy32 : (const T*)P->facy64;
+// Launch a half-sweep, bracketed by timing events when measurement is enabled.
+// kind: 0 column sweep, 1 row sweep, 2 final/transform; bytes: algorithmic HBM bytes.
+int timed_sweep(hpadi_plan_s* P, bool column, const hpadi::SweepArgs& a, int mode, int tin, int tout, int kind,
+                double bytes) {
+    hpadi_plan_s::Rec* r = nullptr;
+    if (P->timing && P->nrec < 65536) {
+        if (P->nrec == P->recs.size()) {
+            hpadi_plan_s::Rec nr{};
+            if (hipEventCreate(&nr.a) != hipSuccess || hipEventCreate(&nr.b) != hipSuccess) return HPADI_EHIP;
+            P->recs.push_back(nr);
+        }
+        r = &P->recs[P->nrec++];
+        r->kind = kind;
+        r->bytes = bytes;
+        if (hipEventRecord(r->a, P->stream) != hipSuccess) return HPADI_EHIP;
+    }
+    const DimDev& d = column ? P->dx.dev : P->dy.dev;
+    if (hpadi::launch_sweep(d, a, mode, tin, tout, column, P->stream) != hipSuccess) return HPADI_EHIP;
+    if (r && hipEventRecord(r->b, P->stream) != hipSuccess) return HPADI_EHIP;
+    return HPADI_OK;
+}
+
+// Arguments common to every sweep along one direction; j selects the shifted
+// factor (j = J: the mass factor alone, for the transforms and the final solve).
+hpadi::SweepArgs sweep_args(const hpadi_plan_s* P, bool column, int j) {
+    hpadi::SweepArgs a{};
+    const DimHost& D = column ? P->dx : P->dy;
+    const DimHost& O = column ? P->dy : P->dx;
+    const FactorLayout& fl = column ? P->flx : P->fly;
+    const double* fac = column ? P->facx64 : P->facy64;
+    const double* coef = column ? P->coefx : P->coefy;
+    a.nlines = O.op.N;
+    a.nh_lines = O.op.nh;
+    a.hpad_lines = O.hpad;
+    a.fl = fl;
+    a.facS = fac + (size_t)j * fl.stride;
+    a.facM = fac + (size_t)P->J * fl.stride;
+    a.coef = coef ? coef + (size_t)j * (D.op.p - 1) * 8 : nullptr;
+    return a;
+}
+
+// G~ = V^{-T} R L^{-1}: column then row transform (mass factors M^x = V^T V, M^y = L^T L).
+int transform_rhs(hpadi_plan_s* P, const double* R, long ldr, int ts) {
+    const double dofs = (double)P->dx.op.N * P->dy.op.N;
+    hpadi::SweepArgs c = sweep_args(P, true, P->J);
+    c.in = R;
+    c.lin = user_layout(P, ldr);
+    c.out = P->T64;
+    c.lout = P->lint;
+    int rc = timed_sweep(P, true, c, hpadi::SWEEP_TRANSFORM, 8, 8, 2, dofs * 16.0);
+    if (rc != HPADI_OK) return rc;
+    hpadi::SweepArgs r = sweep_args(P, false, P->J);
+    r.in = P->T64;
+    r.lin = P->lint;
+    r.out = P->Gt;
+    r.lout = P->lint;
+    return timed_sweep(P, false, r, hpadi::SWEEP_TRANSFORM, 8, ts, 2, dofs * (8.0 + ts));
+}
+
+// Alg. 2 solve loop in balanced coordinates, from G~ (in P->Gt) to U (user layout):
+// U = u (FP64 mode) or U += u (refinement rounds).
+int run_adi(hpadi_plan_s* P, int ts, double* U, long ldu, bool accumulate) {
+    const double dofs = (double)P->dx.op.N * P->dy.op.N;
     const double half = P->omega2 / 2.0;
-    hipStream_t s = P->stream;
+    const hpadi::Layout L = P->lint;
     for (int j = 0; j < P->J; ++j) {
-        // row pass: x = S_y(w/2 + p_j)^{-1} R1 (rows), R2 = G - (K + (w/2 + q_j) M) x
-        hpadi::LinePass r{};
-        r.in = j == 0 ? (const void*)Gin : (const void*)W;
-        r.in_sl = j == 0 ? ldg : P->ldw;
-        r.in_sp = 1;
-        r.out = W;
-        r.out_sl = P->ldw;
-        r.out_sp = 1;
-        r.g = Gin;
-        r.g_sl = ldg;
-        r.g_sp = 1;
-        r.fac = fy + (size_t)j * P->fly.stride;
-        r.fl = P->fly;
+        hpadi::SweepArgs r = sweep_args(P, false, j);
+        r.in = j == 0 ? P->Gt : P->Wk;
+        r.lin = L;
+        r.g = P->Gt;
+        r.lg = L;
+        r.out = P->Wk;
+        r.lout = L;
         r.kappa = 1.0;
         r.tau = half + P->Q[j];
-        r.nlines = Nx;
-        if (hpadi::launch_line_pass(P->dy.dev, r, f32, f32, hpadi::MODE_PRODUCT, false, P->lpb_row, s) != hipSuccess)
-            return HPADI_EHIP;
-        // column pass: x = S_x(w/2 - q_j)^{-1} R2 (columns); R1 = G - (K + (w/2 - p_{j+1}) M) x
-        hpadi::LinePass c{};
-        c.in = W;
-        c.in_sl = 1;
-        c.in_sp = P->ldw;
-        c.out = W;
-        c.out_sl = 1;
-        c.out_sp = P->ldw;
-        c.g = Gin;
-        c.g_sl = 1;
-        c.g_sp = ldg;
-        c.fac = fx + (size_t)j * P->flx.stride;
-        c.fl = P->flx;
+        int rc = timed_sweep(P, false, r, hpadi::SWEEP_FULL, ts, ts, 1, dofs * 3.0 * ts);
+        if (rc != HPADI_OK) return rc;
+        hpadi::SweepArgs c = sweep_args(P, true, j);
+        c.in = P->Wk;
+        c.lin = L;
+        c.g = P->Gt;
+        c.lg = L;
+        c.out = P->Wk;
+        c.lout = L;
         c.kappa = 1.0;
-        c.tau = (j + 1 < P->J) ? half - P->P[j + 1] : 0.0;
-        c.nlines = Ny;
-        const int mode = (j + 1 < P->J) ? hpadi::MODE_PRODUCT : hpadi::MODE_SOLVE;
-        if (hpadi::launch_line_pass(P->dx.dev, c, f32, f32, mode, true, P->lpb_col, s) != hipSuccess)
-            return HPADI_EHIP;
+        const bool last = j + 1 == P->J;
+        c.tau = last ? 0.0 : half - P->P[j + 1];
+        rc = timed_sweep(P, true, c, last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts, 0,
+                         dofs * (last ? 2.0 : 3.0) * ts);
+        if (rc != HPADI_OK) return rc;
     }
-    // U = W_J M_y^{-1} (row solves with the mass factor)
-    hpadi::LinePass f{};
-    f.in = W;
-    f.in_sl = P->ldw;
-    f.in_sp = 1;
+    hpadi::SweepArgs f = sweep_args(P, false, P->J);
+    f.in = P->Wk;
+    f.lin = L;
     f.out = U;
-    f.out_sl = ldu;
-    f.out_sp = 1;
-    f.fac = fy + (size_t)P->J * P->fly.stride;
-    f.fl = P->fly;
-    f.nlines = Nx;
+    f.lout = user_layout(P, ldu);
+    f.accumulate = accumulate ? 1 : 0;
     f.norm_acc = accumulate ? P->acc : nullptr;
     f.wline = P->dx.dev.mdiag;
-    const int mode = accumulate ? hpadi::MODE_ACCUM : hpadi::MODE_SOLVE;
-    if (!accumulate && f32) return HPADI_EINVAL;
-    if (hpadi::launch_line_pass(P->dy.dev, f, f32, f32, mode, false, P->lpb_row, s) != hipSuccess) return HPADI_EHIP;
-    (void)Ny;
-    return HPADI_OK;
+    return timed_sweep(P, false, f, hpadi::SWEEP_FINAL, ts, 8, 2, dofs * (ts + (accumulate ? 16.0 : 8.0)));
 }
 
 // T1 = U M_y, T2 = U A_y (row operators, FP64).
@@ -658,6 +708,13 @@ int row_products(hpadi_plan_s* P, const double* U, long ldu) {
     a.t2 = P->omega2 / 2.0;
     a.nlines = P->dx.op.N;
     return hpadi::launch_op_apply(P->dy.dev, a, false, P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+}
+
+int ensure_fp64_work(hpadi_plan_s* P) {
+    const size_t cnt = (size_t)P->dx.op.N * P->ldw;
+    if (!P->T1 && dmalloc(&P->T1, cnt) != hipSuccess) return HPADI_ENOMEM;
+    if (!P->T2 && dmalloc(&P->T2, cnt) != hipSuccess) return HPADI_ENOMEM;
+    return HPADI_OK;
 }
 
 }  // namespace
@@ -814,48 +871,62 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     if ((rc = make_dim(P->dx, *x)) != HPADI_OK || (rc = make_dim(P->dy, *y)) != HPADI_OK) { plan_free(P); return rc; }
     const int J = P->J;
     if (dmalloc(&P->status, 2 * J + 2) != hipSuccess) { plan_free(P); return HPADI_ENOMEM; }
-    const bool want32 = precision == HPADI_MIXED;
     const double half = omega2 / 2.0;
     // y family: K_y + (w/2 + p_j) M_y for j = 1..J, then M_y
     std::vector<double> ky(J + 1, 1.0), sy(J + 1);
     for (int j = 0; j < J; ++j) sy[j] = half + P->P[j];
     ky[J] = 0.0;
     sy[J] = 1.0;
-    if ((rc = factor_family(P->dy, ky, sy, P->fly, &P->facy64, &P->facy32, want32, P->status, P->stream)) != HPADI_OK) {
+    if ((rc = factor_family(P->dy, ky, sy, P->fly, &P->facy64, P->status, P->stream)) != HPADI_OK) {
         plan_free(P);
         return rc;
     }
-    // x family: K_x + (w/2 - q_j) M_x; shared with y when the operators and shifts coincide
+    // x family: K_x + (w/2 - q_j) M_x, then M_x; shared with y when operators and shifts coincide
     bool shared = same_op(*x, *y);
     for (int j = 0; j < J && shared; ++j) shared = (-P->Q[j] == P->P[j]);
     P->shared = shared;
     if (shared) {
         P->facx64 = P->facy64;
-        P->facx32 = P->facy32;
         P->flx = P->fly;
     } else {
-        std::vector<double> kx(J, 1.0), sx(J);
+        std::vector<double> kx(J + 1, 1.0), sx(J + 1);
         for (int j = 0; j < J; ++j) sx[j] = half - P->Q[j];
-        if ((rc = factor_family(P->dx, kx, sx, P->flx, &P->facx64, &P->facx32, want32, P->status + J + 1,
-                                P->stream)) != HPADI_OK) {
+        kx[J] = 0.0;
+        sx[J] = 1.0;
+        if ((rc = factor_family(P->dx, kx, sx, P->flx, &P->facx64, P->status + J + 1, P->stream)) != HPADI_OK) {
             plan_free(P);
             return rc;
         }
     }
-    // workspace
+    // per-degree coefficient records for the uniform-mesh fast path
+    auto tables = [&](DimHost& D, double* fac, const FactorLayout& fl, double** out) -> int {
+        if (!D.uniform || D.op.p < 2) return HPADI_OK;
+        if (dmalloc(out, (size_t)(J + 1) * (D.op.p - 1) * 8) != hipSuccess) return HPADI_ENOMEM;
+        return hpadi::launch_coef_tables(D.dev, J + 1, fac, fl.stride, fac + (size_t)J * fl.stride, fl, *out,
+                                         P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+    };
+    if ((rc = tables(P->dy, P->facy64, P->fly, &P->coefy)) != HPADI_OK) { plan_free(P); return rc; }
+    if (shared) P->coefx = P->coefy;
+    else if ((rc = tables(P->dx, P->facx64, P->flx, &P->coefx)) != HPADI_OK) { plan_free(P); return rc; }
+    // workspace: internal panel layout (8-column panels, hats padded to a multiple of 8)
     const int Nx = x->N, Ny = y->N;
     P->ldw = ((long)Ny + 63) / 64 * 64;
-    const size_t cnt = (size_t)Nx * P->ldw;
-    bool ok = true;
-    if (precision == HPADI_FP64) {
-        ok = dmalloc(&P->W64, cnt) == hipSuccess;
-    } else {
-        ok = dmalloc(&P->W32, cnt) == hipSuccess && dmalloc(&P->R32, cnt) == hipSuccess;
-    }
+    hpadi::Layout& L = P->lint;
+    L.panel = 1;
+    L.nhr = x->nh;
+    L.nhc = y->nh;
+    L.offr = P->dx.hpad - x->nh;
+    L.offc = P->dy.hpad - y->nh;
+    L.ld = (long)P->dx.Npad * 8;
+    const long panels = (P->dy.Npad + 7) / 8;
+    P->nint = (size_t)panels * L.ld;
+    const size_t ts = precision == HPADI_FP64 ? 8 : 4;
+    bool ok = hipMalloc(&P->Wk, P->nint * ts) == hipSuccess && hipMalloc(&P->Gt, P->nint * ts) == hipSuccess &&
+              dmalloc(&P->T64, P->nint) == hipSuccess;
     ok = ok && dmalloc(&P->acc, 8) == hipSuccess && hipHostMalloc((void**)&P->acc_host, 8 * sizeof(double)) == hipSuccess;
     if (!ok) { plan_free(P); return HPADI_ENOMEM; }
-    P->lpb_col = choose_lpb(x->n, x->p, want32, true, P->opt.lines_col);
-    P->lpb_row = choose_lpb(y->n, y->p, want32, false, P->opt.lines_row);
+    (void)Nx;
+    (void)Ny;
     *out = P;
     return HPADI_OK;
 }
@@ -881,13 +952,10 @@ int hpadi_plan_export_factor(hpadi_plan P, int j, int axis, double* buf, size_t 
     if (!P || !buf || (axis != 0 && axis != 1)) return HPADI_EINVAL;
     const FactorLayout& fl = axis == 0 ? P->flx : P->fly;
     const double* base = axis == 0 ? P->facx64 : P->facy64;
-    int idx = j;
-    if (j == -1) {
-        if (axis != 1) return HPADI_EINVAL;
-        idx = P->J;
-    }
-    if (idx < 0 || idx > P->J || (axis == 0 && idx >= P->J) || len < (size_t)fl.size) return HPADI_EINVAL;
-    if (hipMemcpyAsync(buf, base + (size_t)idx * fl.stride, fl.size * sizeof(double), hipMemcpyDeviceToHost,
+    const int idx = j == -1 ? P->J : j;
+    const size_t doc = (size_t)fl.off_link0 + (fl.off_link0 - fl.off_invd0);  // documented prefix
+    if (idx < 0 || idx > P->J || len < doc) return HPADI_EINVAL;
+    if (hipMemcpyAsync(buf, base + (size_t)idx * fl.stride, doc * sizeof(double), hipMemcpyDeviceToHost,
                        P->stream) != hipSuccess ||
         hipStreamSynchronize(P->stream) != hipSuccess)
         return HPADI_EHIP;
@@ -907,10 +975,9 @@ int hpadi_load(hpadi_plan P, const double* F, int ldf, double* G, int ldg) {
 
 int hpadi_apply(hpadi_plan P, const double* U, int ldu, double* Y, int ldy) {
     if (!P || !U || !Y || ldu < P->dy.op.N || ldy < P->dy.op.N) return HPADI_EINVAL;
-    const size_t cnt = (size_t)P->dx.op.N * P->ldw;
-    if (!P->T1 && (dmalloc(&P->T1, cnt) != hipSuccess || dmalloc(&P->T2, cnt) != hipSuccess)) return HPADI_ENOMEM;
-    int rc = row_products(P, U, ldu);
+    int rc = ensure_fp64_work(P);
     if (rc != HPADI_OK) return rc;
+    if ((rc = row_products(P, U, ldu)) != HPADI_OK) return rc;
     hpadi::Residual r{};
     r.G = nullptr;
     r.T1 = P->T1;
@@ -935,24 +1002,24 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
     const int Nx = P->dx.op.N, Ny = P->dy.op.N;
     int rc = HPADI_OK;
     if (P->precision == HPADI_FP64) {
-        rc = run_adi<double>(P, G, ldg, P->W64, U, ldu, false);
+        if ((rc = transform_rhs(P, G, ldg, 8)) != HPADI_OK) return rc;
+        if ((rc = run_adi(P, 8, U, ldu, false)) != HPADI_OK) return rc;
         st.rounds = 1;
         st.iters = P->J;
         st.est_rel_err = P->tol;
     } else {
         // Iterative refinement: U = 0; repeat { delta = ADI_fp32(r); U += delta; r = G - A U (FP64) }.
-        const size_t cnt = (size_t)Nx * P->ldw;
-        if (!P->T1 && (dmalloc(&P->T1, cnt) != hipSuccess || dmalloc(&P->T2, cnt) != hipSuccess)) return HPADI_ENOMEM;
+        if ((rc = ensure_fp64_work(P)) != HPADI_OK) return rc;
+        if (!P->R64 && dmalloc(&P->R64, (size_t)Nx * P->ldw) != hipSuccess) return HPADI_ENOMEM;
         if (hpadi::launch_zero_f64(U, ldu, Nx, Ny, s) != hipSuccess) return HPADI_EHIP;
-        if (hpadi::launch_convert_f64_f32(G, ldg, P->R32, P->ldw, Nx, Ny, nullptr, nullptr, nullptr, s) != hipSuccess)
-            return HPADI_EHIP;
-        double nd_prev = 0.0, est = 1.0, gnorm = 0.0;
+        double nd_prev = 0.0, est = 1.0;
         const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
         int k = 0;
         bool done = false;
-        for (k = 1; k <= maxr && !done; ++k) {
+        for (k = 1; k <= maxr; ++k) {
             if (hipMemsetAsync(P->acc, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
-            if ((rc = run_adi<float>(P, P->R32, P->ldw, P->W32, U, ldu, true)) != HPADI_OK) return rc;
+            if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, 4)) != HPADI_OK) return rc;
+            if ((rc = run_adi(P, 4, U, ldu, true)) != HPADI_OK) return rc;
             st.iters += P->J;
             if (P->opt.fixed_rounds <= 0) {
                 if (hipMemcpyAsync(P->acc_host, P->acc, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -961,21 +1028,15 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
                 const double nd = std::sqrt(std::max(P->acc_host[0], 0.0));
                 const double nu = std::sqrt(std::max(P->acc_host[1], 0.0));
                 if (k > 1) {
-                    gnorm = std::sqrt(std::max(P->acc_host[3], 0.0));
+                    const double gnorm = std::sqrt(std::max(P->acc_host[3], 0.0));
                     st.res_rel = gnorm > 0 ? std::sqrt(std::max(P->acc_host[2], 0.0)) / gnorm : 0.0;
                 }
                 // error after this round ~ rho ||delta_k||, rho the observed contraction per round
-                const double rho = (k == 1) ? std::max(P->opt.inner_tol, 2e-5)
+                const double rho = (k == 1) ? std::max(P->opt.inner_tol, 1e-6)
                                             : std::min(1.0, nd / std::max(nd_prev, 1e-300));
                 est = nu > 0 ? rho * nd / nu : 0.0;
                 nd_prev = nd;
-                if (!std::isfinite(est)) {
-                    st.est_rel_err = est;
-                    st.rounds = k;
-                    st.status = HPADI_ENOCONV;
-                    if (stats) *stats = st;
-                    return HPADI_ENOCONV;
-                }
+                if (!std::isfinite(est)) break;
                 if (est <= P->tol) {
                     done = true;
                     break;
@@ -983,7 +1044,7 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
             } else if (k == maxr) {
                 break;
             }
-            // r = G - A U in FP64, stored as the next FP32 right-hand side
+            // r = G - A U in FP64
             if ((rc = row_products(P, U, ldu)) != HPADI_OK) return rc;
             if (hipMemsetAsync(P->acc + 2, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
             hpadi::Residual r{};
@@ -992,8 +1053,8 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
             r.T1 = P->T1;
             r.T2 = P->T2;
             r.t_ld = P->ldw;
-            r.r32 = P->R32;
-            r.r32_ld = P->ldw;
+            r.r64 = P->R64;
+            r.r64_ld = P->ldw;
             r.ax_k = 1.0;
             r.ax_t = P->omega2 / 2.0;
             r.alpha = 1.0;
@@ -1011,6 +1072,34 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
     st.status = rc;
     if (stats) *stats = st;
     return rc;
+}
+
+int hpadi_plan_timing(hpadi_plan P, int enable) {
+    if (!P) return HPADI_EINVAL;
+    if (enable) P->nrec = 0;
+    P->timing = enable != 0;
+    return HPADI_OK;
+}
+
+int hpadi_plan_timing_read(hpadi_plan P, double ms[3], double bytes[3], int count[3]) {
+    if (!P) return HPADI_EINVAL;
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return HPADI_EHIP;
+    double t[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+    int c[3] = {0, 0, 0};
+    for (size_t i = 0; i < P->nrec; ++i) {
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, P->recs[i].a, P->recs[i].b) != hipSuccess) return HPADI_EHIP;
+        const int k = P->recs[i].kind;
+        t[k] += e;
+        b[k] += P->recs[i].bytes;
+        c[k] += 1;
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (ms) ms[k] = t[k];
+        if (bytes) bytes[k] = b[k];
+        if (count) count[k] = c[k];
+    }
+    return HPADI_OK;
 }
 
 void hpadi_plan_destroy(hpadi_plan P) {

@@ -32,6 +32,8 @@ struct FactorLayout {
     int off_cpl;    // coupling to hats: index 4e + 2 pi + side
     int off_invd0;  // hat factor 1/diag, n_h
     int off_link0;  // hat factor L0[h, h-1], n_h
+    int off_d;      // diagonal of L at bubble (m, e) (= 1 / invd), (p-1) n
+    int off_d0;     // diagonal of the hat factor L0, n_h
     int size;       // used length
     int stride;     // distance between consecutive records (multiple of 64)
 };
@@ -44,7 +46,9 @@ inline FactorLayout make_factor_layout(int n, int p, int nh) {
     L.off_cpl = 2 * L.nb;
     L.off_invd0 = 2 * L.nb + 4 * n;
     L.off_link0 = L.off_invd0 + nh;
-    L.size = L.off_link0 + nh;
+    L.off_d = L.off_link0 + nh;
+    L.off_d0 = L.off_d + L.nb;
+    L.size = L.off_d0 + nh;
     L.stride = (L.size + 63) / 64 * 64;
     return L;
 }
@@ -54,27 +58,42 @@ inline FactorLayout make_factor_layout(int n, int p, int nh) {
 hipError_t launch_factor(const DimDev& d, int nf, const double* kappa_dev, const double* sigma_dev,
                          double* fac64, float* fac32, int stride, int* status_dev, hipStream_t s);
 
-// One ADI half-sweep over all lines of an array: per line x = S^{-1} b with the
-// structured factor, then the output chosen by mode.
-enum PassMode { MODE_PRODUCT = 0, MODE_SOLVE = 1, MODE_ACCUM = 2 };
-struct LinePass {
-    const void* in;       // TW: right-hand sides b
-    long in_sl, in_sp;    // strides: line, position
-    void* out;            // TW (PRODUCT/SOLVE) or double (ACCUM)
-    long out_sl, out_sp;
-    const void* g;        // TG: G (PRODUCT only)
-    long g_sl, g_sp;
-    const void* fac;      // TW factor record
-    FactorLayout fl;
-    double kappa, tau;    // PRODUCT: out = G - (kappa K + tau M) x
-    int nlines;
-    double* norm_acc;     // ACCUM: accumulates [sum w dx^2, sum w u^2] (may be NULL)
-    const double* wline;  // ACCUM: weight per line (diag of M on the other axis)
+// Entry (i, j) of an Nx x Ny array: row-major (ptr[i*ld + j]) or the internal
+// 8-column panel layout (panel j/8 at offset (j/8)*ld, row i at 8 i within it),
+// with row/column indices past the hats shifted by offr/offc (alignment padding).
+struct Layout {
+    long ld;
+    int panel;
+    int nhr, nhc;    // hats along x (rows) and y (columns)
+    int offr, offc;  // padding shift of indices >= nhr / >= nhc
 };
-hipError_t launch_line_pass(const DimDev& d, const LinePass& a, bool fp32, bool g_fp32, int mode,
-                            bool column, int lines_per_block, hipStream_t s);
-// Largest workgroup the line pass accepts for degree p (threads = lines_per_block * n).
-int line_pass_max_threads(int p, bool fp32);
+
+// Half-sweeps in mass-balanced coordinates (sweep.hip).
+enum SweepMode { SWEEP_FULL = 0, SWEEP_SOLVE = 1, SWEEP_TRANSFORM = 2, SWEEP_FINAL = 3 };
+struct SweepArgs {
+    const void* in; Layout lin;     // y (FULL, SOLVE), right-hand side (TRANSFORM), w (FINAL)
+    const void* g; Layout lg;       // balanced right-hand side G~ (FULL)
+    void* out; Layout lout;
+    const double* facS;             // factor of the shifted operator (FULL, SOLVE)
+    const double* facM;             // factor of this direction's mass matrix
+    const double* coef;             // uniform meshes: per-degree coefficient records (8 doubles per m), or NULL
+    FactorLayout fl;
+    double kappa, tau;              // FULL: product kappa K + tau M
+    int nlines;                     // lines of the problem
+    int nh_lines, hpad_lines;       // hats along the line index, and their padded count
+    int accumulate;                 // FINAL: U += u (1) or U = u (0)
+    double* norm_acc;               // FINAL: [sum w u^2, sum w U^2] or NULL
+    const double* wline;            // FINAL: weight per line
+};
+hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
+                        hipStream_t s);
+// Per-degree coefficient records for a uniform mesh, for nf shifted factors (records f * stride of
+// facS) each paired with the mass factor facM: out[(f (p-1) + m) * 8 + k] =
+//   S.invd, S.link, M.d, M.link, M.invd (at degree m, element 0), 4/((2m+3) delta),
+//   2 delta/((2m+1)(2m+3)(2m+5)), -delta/((2m+3)(2m+5)(2m+7)).
+hipError_t launch_coef_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
+                              FactorLayout fl, double* out, hipStream_t s);
+int sweep_threads(int n);
 
 // Banded operator along lines, elementwise: out = (kappa K + tau M) x per line
 // (and optionally a second output with (kappa2, tau2)).  FP64.

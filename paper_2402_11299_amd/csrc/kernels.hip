@@ -4,11 +4,7 @@
 //  * factor_kernel   reverse Cholesky of kappa K + sigma M (Sec. 4, Alg. 1), one
 //                    workgroup per matrix, one thread per (element, parity) chain,
 //                    the hat Schur complement in FP64 by one thread.
-//  * line_pass       one ADI half-sweep (Sec. 5, Alg. 2): per line a solve with the
-//                    structured factor (corollary of Sec. 4) fused with the banded
-//                    product of the next half-step.  One thread owns one element of
-//                    one line and keeps both of its bubble chains in registers; the
-//                    hat system is solved per line through LDS.
+//  * the ADI half-sweeps themselves are in sweep.hip.
 //  * op_apply, residual, load: elementwise gathers of the banded operators.
 //
 // Coefficient order (per dimension, Sec. 2.2): hats 0..nh-1, then bubble (m, e)
@@ -65,6 +61,7 @@ __global__ void __launch_bounds__(256) factor_kernel(DimDev d, const double* __r
             }
             const double dd = sqrt(a);
             F[fl.off_invd + m * n + e] = 1.0 / dd;
+            F[fl.off_d + m * n + e] = dd;
             dup = dd;
             if (s == 0) dhead = dd;
         }
@@ -115,6 +112,7 @@ __global__ void __launch_bounds__(256) factor_kernel(DimDev d, const double* __r
             }
             const double dd = sqrt(a);
             F[fl.off_invd0 + h] = 1.0 / dd;
+            F[fl.off_d0 + h] = dd;
             dup = dd;
         }
         if (nh > 0) F[fl.off_link0] = 0.0;
@@ -127,272 +125,10 @@ __global__ void __launch_bounds__(256) factor_kernel(DimDev d, const double* __r
     }
 }
 
-// ---------------------------------------------------------------------------
-// ADI half-sweep over lines.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ const T* tables(const DimDev& d);
-template <>
-__device__ __forceinline__ const double* tables<double>(const DimDev& d) {
-    return d.tab64;
-}
-template <>
-__device__ __forceinline__ const float* tables<float>(const DimDev& d) {
-    return d.tab32;
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
-}
-
-constexpr int max_threads_for(int cl, int tsize) {
-    return (2 * cl * tsize / 4) <= 64 ? 1024 : ((2 * cl * tsize / 4) <= 128 ? 512 : 256);
-}
-
-template <typename T, int CL, int MODE, bool COL>
-__global__ void __launch_bounds__(max_threads_for(CL, sizeof(T)))
-    line_pass_kernel(DimDev d, LinePass a, int lpb) {
-    extern __shared__ unsigned char smem_raw[];
-    T* sm = reinterpret_cast<T*>(smem_raw);
-    const int n = d.n, p = d.p, nh = d.nh;
-    const int hs = nh + 1;
-    T* hb = sm;             // [lpb][hs]: hat right-hand side, then hat solution
-    T* hd = sm + lpb * hs;  // [lpb][n][2]: chain heads (y, then x)
-
-    const int t = threadIdx.x;
-    int l, e;
-    if (COL) {
-        l = t % lpb;
-        e = t / lpb;
-    } else {
-        e = t % n;
-        l = t / n;
-    }
-    const int line = blockIdx.x * lpb + l;
-    const bool act = line < a.nlines;
-    const int le = p / 2, lo = (p - 1) / 2;
-
-    const T* fac = reinterpret_cast<const T*>(a.fac);
-    const T* invd = fac + a.fl.off_invd;
-    const T* link = fac + a.fl.off_link;
-    const T* cpl = fac + a.fl.off_cpl;
-    const T* invd0 = fac + a.fl.off_invd0;
-    const T* link0 = fac + a.fl.off_link0;
-
-    T ev[CL], od[CL];
-    T* hbl = hb + l * hs;
-    T* hdl = hd + l * 2 * n;
-
-    // ---- load the line: both chains of element e into registers, hats into LDS
-    if (act) {
-        const T* in = reinterpret_cast<const T*>(a.in) + (long)line * a.in_sl;
-#pragma unroll
-        for (int s = 0; s < CL; ++s) {
-            if (s < le) ev[s] = in[(long)(nh + (2 * s) * n + e) * a.in_sp];
-            if (s < lo) od[s] = in[(long)(nh + (2 * s + 1) * n + e) * a.in_sp];
-        }
-        if (e < nh) hbl[e] = in[(long)e * a.in_sp];
-        if (e == 0 && nh == n + 1) hbl[n] = in[(long)n * a.in_sp];
-        // ---- L~^T y = b along each chain, highest degree first
-#pragma unroll
-        for (int s = CL - 1; s >= 0; --s) {
-            if (s < le) {
-                T v = ev[s];
-                if (s + 1 < CL) {
-                    if (s + 1 < le) v -= link[(2 * s + 2) * n + e] * ev[s + 1];
-                }
-                ev[s] = v * invd[(2 * s) * n + e];
-            }
-            if (s < lo) {
-                T v = od[s];
-                if (s + 1 < CL) {
-                    if (s + 1 < lo) v -= link[(2 * s + 3) * n + e] * od[s + 1];
-                }
-                od[s] = v * invd[(2 * s + 1) * n + e];
-            }
-        }
-        hdl[2 * e + 0] = le > 0 ? ev[0] : T(0);
-        hdl[2 * e + 1] = lo > 0 ? od[0] : T(0);
-    }
-    __syncthreads();
-    // ---- hat right-hand side b_h - (C^T y)_h
-    if (act) {
-        for (int h = e; h < nh; h += n) {
-            const int v = vertex_of_hat(d.bc, h);
-            T acc = hbl[h];
-            if (v >= 1) {
-                const int q = v - 1;
-                acc -= cpl[4 * q + 1] * hdl[2 * q] + cpl[4 * q + 3] * hdl[2 * q + 1];
-            }
-            if (v <= n - 1) {
-                const int q = v;
-                acc -= cpl[4 * q + 0] * hdl[2 * q] + cpl[4 * q + 2] * hdl[2 * q + 1];
-            }
-            hbl[h] = acc;
-        }
-    }
-    __syncthreads();
-    // ---- hat block: L0^T z = bhat (last hat first), then L0 x = z
-    if (act && e == 0) {
-        T z = T(0);
-        for (int h = nh - 1; h >= 0; --h) {
-            T v = hbl[h];
-            if (h + 1 < nh) v -= link0[h + 1] * z;
-            z = v * invd0[h];
-            hbl[h] = z;
-        }
-        T x = T(0);
-        for (int h = 0; h < nh; ++h) {
-            T v = hbl[h];
-            if (h > 0) v -= link0[h] * x;
-            x = v * invd0[h];
-            hbl[h] = x;
-        }
-    }
-    __syncthreads();
-    // ---- L~ x = y - C x_h along each chain, lowest degree first
-    T xl = T(0), xr = T(0);
-    if (act) {
-        if (vertex_is_hat(d.bc, n, e)) xl = hbl[hat_of_vertex(d.bc, e)];
-        if (vertex_is_hat(d.bc, n, e + 1)) xr = hbl[hat_of_vertex(d.bc, e + 1)];
-        if (le > 0) ev[0] = (ev[0] - cpl[4 * e + 0] * xl - cpl[4 * e + 1] * xr) * invd[e];
-        if (lo > 0) od[0] = (od[0] - cpl[4 * e + 2] * xl - cpl[4 * e + 3] * xr) * invd[n + e];
-#pragma unroll
-        for (int s = 1; s < CL; ++s) {
-            if (s < le) ev[s] = (ev[s] - link[(2 * s) * n + e] * ev[s - 1]) * invd[(2 * s) * n + e];
-            if (s < lo) od[s] = (od[s] - link[(2 * s + 1) * n + e] * od[s - 1]) * invd[(2 * s + 1) * n + e];
-        }
-        hdl[2 * e + 0] = le > 0 ? ev[0] : T(0);
-        hdl[2 * e + 1] = lo > 0 ? od[0] : T(0);
-    }
-    __syncthreads();
-
-    // ---- outputs
-    if (act && MODE == MODE_PRODUCT) {
-        // out = G - (kappa K + tau M) x   (App. A entries)
-        const T* G = reinterpret_cast<const T*>(a.g) + (long)line * a.g_sl;
-        T* out = reinterpret_cast<T*>(a.out) + (long)line * a.out_sl;
-        const T* tb = tables<T>(d);
-        const T* kd = tb;
-        const T* md = tb + d.tabstride;
-        const T* mo = tb + 2 * d.tabstride;
-        const T kap = (T)a.kappa, tau = (T)a.tau;
-        const T de = (T)d.delta[e], ide = (T)d.invdelta[e];
-        const T tde = tau * de;
-#pragma unroll
-        for (int s = 0; s < CL; ++s) {
-            if (s < le) {
-                const int m = 2 * s;
-                T y = (kap * kd[m] * ide + tde * md[m]) * ev[s];
-                if (s > 0) y += tde * mo[m - 2] * ev[s - 1];
-                if (s + 1 < CL) {
-                    if (s + 1 < le) y += tde * mo[m] * ev[s + 1];
-                }
-                if (s == 0) y += tde * (T(1) / T(6)) * (xl + xr);
-                const long pos = nh + m * n + e;
-                out[pos * a.out_sp] = G[pos * a.g_sp] - y;
-            }
-            if (s < lo) {
-                const int m = 2 * s + 1;
-                T y = (kap * kd[m] * ide + tde * md[m]) * od[s];
-                if (s > 0) y += tde * mo[m - 2] * od[s - 1];
-                if (s + 1 < CL) {
-                    if (s + 1 < lo) y += tde * mo[m] * od[s + 1];
-                }
-                if (s == 0) y += tde * (T(1) / T(30)) * (xr - xl);
-                const long pos = nh + m * n + e;
-                out[pos * a.out_sp] = G[pos * a.g_sp] - y;
-            }
-        }
-        for (int h = e; h < nh; h += n) {
-            const int v = vertex_of_hat(d.bc, h);
-            const T xh = hbl[h];
-            T y = T(0);
-            if (v >= 1) {
-                const int q = v - 1;
-                const T dq = (T)d.delta[q], idq = (T)d.invdelta[q];
-                y += (kap * idq + tau * dq * (T(1) / T(3))) * xh;
-                if (vertex_is_hat(d.bc, n, v - 1)) y += (-kap * idq + tau * dq * (T(1) / T(6))) * hbl[h - 1];
-                y += tau * dq * (hdl[2 * q] * (T(1) / T(6)) + hdl[2 * q + 1] * (T(1) / T(30)));
-            }
-            if (v <= n - 1) {
-                const int q = v;
-                const T dq = (T)d.delta[q], idq = (T)d.invdelta[q];
-                y += (kap * idq + tau * dq * (T(1) / T(3))) * xh;
-                if (vertex_is_hat(d.bc, n, v + 1)) y += (-kap * idq + tau * dq * (T(1) / T(6))) * hbl[h + 1];
-                y += tau * dq * (hdl[2 * q] * (T(1) / T(6)) - hdl[2 * q + 1] * (T(1) / T(30)));
-            }
-            out[(long)h * a.out_sp] = G[(long)h * a.g_sp] - y;
-        }
-    } else if (act && MODE == MODE_SOLVE) {
-        T* out = reinterpret_cast<T*>(a.out) + (long)line * a.out_sl;
-#pragma unroll
-        for (int s = 0; s < CL; ++s) {
-            if (s < le) out[(long)(nh + (2 * s) * n + e) * a.out_sp] = ev[s];
-            if (s < lo) out[(long)(nh + (2 * s + 1) * n + e) * a.out_sp] = od[s];
-        }
-        for (int h = e; h < nh; h += n) out[(long)h * a.out_sp] = hbl[h];
-    } else if (MODE == MODE_ACCUM) {
-        // U += x in FP64, with weighted sums of squares of the update and of U
-        double sdx = 0.0, su = 0.0;
-        if (act) {
-        double* out = reinterpret_cast<double*>(a.out) + (long)line * a.out_sl;
-        const double* w = d.mdiag;
-#pragma unroll
-        for (int s = 0; s < CL; ++s) {
-            if (s < le) {
-                const long pos = nh + (2 * s) * n + e;
-                const double dx = (double)ev[s];
-                const double u = out[pos * a.out_sp] + dx;
-                out[pos * a.out_sp] = u;
-                sdx += w[pos] * dx * dx;
-                su += w[pos] * u * u;
-            }
-            if (s < lo) {
-                const long pos = nh + (2 * s + 1) * n + e;
-                const double dx = (double)od[s];
-                const double u = out[pos * a.out_sp] + dx;
-                out[pos * a.out_sp] = u;
-                sdx += w[pos] * dx * dx;
-                su += w[pos] * u * u;
-            }
-        }
-        for (int h = e; h < nh; h += n) {
-            const double dx = (double)hbl[h];
-            const double u = out[(long)h * a.out_sp] + dx;
-            out[(long)h * a.out_sp] = u;
-            sdx += w[h] * dx * dx;
-            su += w[h] * u * u;
-        }
-        if (a.norm_acc) {
-            const double wl = a.wline[line];
-            sdx *= wl;
-            su *= wl;
-        }
-        }
-        if (a.norm_acc) {
-            // block reduction through LDS (the launch sizes LDS for 2 doubles per thread)
-            __syncthreads();
-            double* red = reinterpret_cast<double*>(smem_raw);
-            red[2 * t] = sdx;
-            red[2 * t + 1] = su;
-            __syncthreads();
-            for (int w = blockDim.x; w > 1; w = (w + 1) / 2) {
-                const int half = (w + 1) / 2;
-                if (t + half < w) {
-                    red[2 * t] += red[2 * (t + half)];
-                    red[2 * t + 1] += red[2 * (t + half) + 1];
-                }
-                __syncthreads();
-            }
-            if (t == 0) {
-                atomicAdd(a.norm_acc + 0, red[0]);
-                atomicAdd(a.norm_acc + 1, red[1]);
-            }
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -478,29 +214,39 @@ __global__ void __launch_bounds__(256) op_apply_cols(DimDev d, OpApply a) {
 
 // r[i][j] = alpha G[i][j] + beta ((ax_k K + ax_t M) T1 + M T2)[i][j], operators along x.
 __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
+    // A block owns 256 columns and the rows blockIdx.y, blockIdx.y + gridDim.y, ...;
+    // the weighted sums of squares are reduced per block (one atomic pair per block).
+    __shared__ double red[2][4];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
     double sr = 0.0, sg = 0.0;
-    if (j < a.ncols && i < dx.N) {
-        double K1, M1, K2, M2;
-        gather_km(dx, a.T1 + j, a.t_ld, i, K1, M1);
-        gather_km(dx, a.T2 + j, a.t_ld, i, K2, M2);
-        const double g = a.G ? a.G[(long)i * a.g_ld + j] : 0.0;
-        const double r = a.alpha * g + a.beta * (a.ax_k * K1 + a.ax_t * M1 + M2);
-        if (a.r64) a.r64[(long)i * a.r64_ld + j] = r;
-        if (a.r32) a.r32[(long)i * a.r32_ld + j] = (float)r;
-        if (a.norm_acc) {
-            const double w = dx.mdiag[i] * a.wcol[j];
-            sr = w * r * r;
-            sg = w * g * g;
+    if (j < a.ncols) {
+        for (int i = blockIdx.y; i < dx.N; i += gridDim.y) {
+            double K1, M1, K2, M2;
+            gather_km(dx, a.T1 + j, a.t_ld, i, K1, M1);
+            gather_km(dx, a.T2 + j, a.t_ld, i, K2, M2);
+            const double g = a.G ? a.G[(long)i * a.g_ld + j] : 0.0;
+            const double r = a.alpha * g + a.beta * (a.ax_k * K1 + a.ax_t * M1 + M2);
+            if (a.r64) a.r64[(long)i * a.r64_ld + j] = r;
+            if (a.r32) a.r32[(long)i * a.r32_ld + j] = (float)r;
+            if (a.norm_acc) {
+                const double w = dx.mdiag[i] * a.wcol[j];
+                sr += w * r * r;
+                sg += w * g * g;
+            }
         }
     }
     if (a.norm_acc) {
         sr = wave_sum(sr);
         sg = wave_sum(sg);
+        const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
-            atomicAdd(a.norm_acc + 0, sr);
-            atomicAdd(a.norm_acc + 1, sg);
+            red[0][w] = sr;
+            red[1][w] = sg;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            atomicAdd(a.norm_acc + 0, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+            atomicAdd(a.norm_acc + 1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
         }
     }
 }
@@ -571,46 +317,9 @@ __global__ void __launch_bounds__(256) zero_kernel(double* dst, long ld, int row
     if (j < cols && i < rows) dst[(long)i * ld + j] = 0.0;
 }
 
-template <typename T, int CL, int MODE, bool COL>
-hipError_t launch_lp(const DimDev& d, const LinePass& a, int lpb, hipStream_t s) {
-    const int threads = lpb * d.n;
-    if (threads > max_threads_for(CL, sizeof(T)) || threads <= 0) return hipErrorInvalidValue;
-    const int blocks = (a.nlines + lpb - 1) / lpb;
-    size_t shm = (size_t)lpb * (d.nh + 1 + 2 * d.n) * sizeof(T);
-    if (MODE == MODE_ACCUM && shm < (size_t)threads * 2 * sizeof(double)) shm = (size_t)threads * 2 * sizeof(double);
-    hipLaunchKernelGGL((line_pass_kernel<T, CL, MODE, COL>), dim3(blocks), dim3(threads), shm, s, d, a, lpb);
-    return hipGetLastError();
-}
-
-template <typename T, int CL>
-hipError_t dispatch_mode(const DimDev& d, const LinePass& a, int mode, bool col, int lpb, hipStream_t s) {
-    if (mode == MODE_PRODUCT) return col ? launch_lp<T, CL, MODE_PRODUCT, true>(d, a, lpb, s)
-                                         : launch_lp<T, CL, MODE_PRODUCT, false>(d, a, lpb, s);
-    if (mode == MODE_SOLVE) return col ? launch_lp<T, CL, MODE_SOLVE, true>(d, a, lpb, s)
-                                       : launch_lp<T, CL, MODE_SOLVE, false>(d, a, lpb, s);
-    return col ? launch_lp<T, CL, MODE_ACCUM, true>(d, a, lpb, s) : launch_lp<T, CL, MODE_ACCUM, false>(d, a, lpb, s);
-}
-
-template <typename T>
-hipError_t dispatch_cl(const DimDev& d, const LinePass& a, int mode, bool col, int lpb, hipStream_t s) {
-    const int need = d.p / 2;
-    if (need <= 4) return dispatch_mode<T, 4>(d, a, mode, col, lpb, s);
-    if (need <= 8) return dispatch_mode<T, 8>(d, a, mode, col, lpb, s);
-    if (need <= 16) return dispatch_mode<T, 16>(d, a, mode, col, lpb, s);
-    if (need <= 32) return dispatch_mode<T, 32>(d, a, mode, col, lpb, s);
-    if (need <= 64) return dispatch_mode<T, 64>(d, a, mode, col, lpb, s);
-    return hipErrorInvalidValue;
-}
-
 inline dim3 grid2(int inner, int outer) { return dim3((inner + 255) / 256, outer); }
 
 }  // namespace
-
-int line_pass_max_threads(int p, bool fp32) {
-    const int need = p / 2;
-    const int cl = need <= 4 ? 4 : need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 64;
-    return max_threads_for(cl, fp32 ? 4 : 8);
-}
 
 hipError_t launch_factor(const DimDev& d, int nf, const double* kappa_dev, const double* sigma_dev, double* fac64,
                          float* fac32, int stride, int* status_dev, hipStream_t s) {
@@ -619,13 +328,6 @@ hipError_t launch_factor(const DimDev& d, int nf, const double* kappa_dev, const
     hipLaunchKernelGGL(factor_kernel, dim3(nf), dim3(256), 0, s, d, kappa_dev, sigma_dev, fac64, fac32, fl,
                        status_dev);
     return hipGetLastError();
-}
-
-hipError_t launch_line_pass(const DimDev& d, const LinePass& a, bool fp32, bool /*g_fp32*/, int mode, bool column,
-                            int lines_per_block, hipStream_t s) {
-    if (a.nlines <= 0) return hipSuccess;
-    return fp32 ? dispatch_cl<float>(d, a, mode, column, lines_per_block, s)
-                : dispatch_cl<double>(d, a, mode, column, lines_per_block, s);
 }
 
 hipError_t launch_op_apply(const DimDev& d, const OpApply& a, bool column, hipStream_t s) {
@@ -639,7 +341,8 @@ hipError_t launch_op_apply(const DimDev& d, const OpApply& a, bool column, hipSt
 
 hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s) {
     if (a.ncols <= 0 || dx.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(residual_kernel, grid2(a.ncols, dx.N), dim3(256), 0, s, dx, a);
+    hipLaunchKernelGGL(residual_kernel, dim3((a.ncols + 255) / 256, dx.N < 128 ? dx.N : 128), dim3(256), 0, s, dx,
+                       a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,599 @@
+// ADI half-sweeps in mass-balanced coordinates (gfx950).
+//
+// The generalised ADI of Sec. 5 (Alg. 2) is, by the lemma that proves its error
+// bound, the standard ADI for X = V U L^T, where M^x = V^T V and M^y = L^T L are
+// the reverse Cholesky factors of the two mass matrices (Sec. 4).  In these
+// coordinates a half-sweep along one direction, with S = K + sigma M and mass
+// factor Lm of that direction, is
+//
+//   z = Lm^T y,   w = S^{-1} z,   out = g - Lm^{-T} (kappa K + tau M) w,
+//
+// (kappa K + tau M) being the product of the next half-step.  Every stored array
+// (y, g, out) is then balanced: a relative rounding of its entries is a relative
+// error in the norm of the ADI lemma, which is what lets the bulk of the data
+// live in FP32 without the mass matrix amplifying the rounding.  All arithmetic
+// here is FP64 (registers are not the bottleneck of a bandwidth-bound sweep).
+//
+// Work decomposition: a workgroup owns 8 lines (one 8-wide panel of the internal
+// layout) and one thread owns one bubble chain (element e, parity pi) of one
+// line, kept in registers.  Chain c = pi n + e of a line holds positions
+// nh + 2 s n + c, s = 0, 1, ..., so the 2n chains of a step are consecutive and
+// each wavefront reads 8 lines x 8 consecutive positions: 256 contiguous bytes
+// (FP32) in both sweep directions.  The hat block of each line (the Schur
+// complement of Alg. 1, n_h <= 65 unknowns) is solved by one wavefront per line
+// as parallel prefix/suffix scans of affine maps, with the hat factors staged in
+// LDS.
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace hpadi {
+
+namespace {
+
+__device__ __forceinline__ bool vhat(int bc, int n, int v) { return bc == 0 ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n); }
+__device__ __forceinline__ int hov(int bc, int v) { return bc == 0 ? v - 1 : v; }
+__device__ __forceinline__ int voh(int bc, int h) { return bc == 0 ? h + 1 : h; }
+
+__device__ __forceinline__ long addr(const Layout& L, int i, int j) {
+    const int ii = i >= L.nhr ? i + L.offr : i;
+    const int jj = j >= L.nhc ? j + L.offc : j;
+    return L.panel ? (long)(jj >> 3) * L.ld + (long)ii * 8 + (jj & 7) : (long)ii * L.ld + jj;
+}
+
+constexpr int sweep_max_threads(int cl) { return cl <= 32 ? 1024 : 512; }
+
+// Staged hat data of one factor: 1/diag, diag, sub-diagonal of L0, coupling C.
+struct HatF {
+    double* invd0;
+    double* d0;
+    double* link0;  // link0[h] = L0[h][h-1]; link0[nh] = 0 (sentinel)
+    double* cpl;    // 4n
+};
+
+// Suffix scan over lanes of affine maps z = a + b z_next (lane k composes with
+// lane k+1, k+2, ...): afterwards a = value of the recurrence run from the last
+// lane down to k with terminal value 0.
+__device__ __forceinline__ void suffix_scan(double& a, double& b, int lane, int nl) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double a2 = __shfl_down(a, d, 64);
+        const double b2 = __shfl_down(b, d, 64);
+        if (lane + d < nl) {
+            a = a + b * a2;
+            b = b * b2;
+        }
+    }
+}
+// Prefix scan: x = a + b x_prev, composed with lanes k-1, k-2, ...
+__device__ __forceinline__ void prefix_scan(double& a, double& b, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double a2 = __shfl_up(a, d, 64);
+        const double b2 = __shfl_up(b, d, 64);
+        if (lane >= d) {
+            a = a + b * a2;
+            b = b * b2;
+        }
+    }
+}
+
+// Hat-block backward solve L0^T z = r for one line, by one full wavefront.
+// r: LDS hat array (nh <= 65), overwritten with z.  Lane k owns hat k; lane 63
+// also owns hat 64 when nh = 65.
+__device__ __forceinline__ void hat_backward(double* r, const HatF& F, int nh, int lane) {
+    const int nl = nh < 64 ? nh : 64;
+    double a = 0.0, b = 1.0;
+    double a64 = 0.0;
+    if (lane < nl) {
+        a = r[lane] * F.invd0[lane];
+        b = -F.link0[lane + 1] * F.invd0[lane];
+        if (lane == 63 && nh == 65) {
+            a64 = r[64] * F.invd0[64];
+            a = a + b * a64;  // compose with hat 64 (whose own map is constant)
+            b = 0.0;
+        }
+    }
+    suffix_scan(a, b, lane, nl);
+    if (lane < nl) r[lane] = a;
+    if (lane == 63 && nh == 65) r[64] = a64;
+}
+
+// Hat-block forward solve L0 x = z for one line (in place on r).
+__device__ __forceinline__ void hat_forward(double* r, const HatF& F, int nh, int lane) {
+    const int nl = nh < 64 ? nh : 64;
+    double a = 0.0, b = 0.0;
+    if (lane < nl) {
+        a = r[lane] * F.invd0[lane];
+        b = -F.link0[lane] * F.invd0[lane];
+    }
+    prefix_scan(a, b, lane);
+    if (lane < nl) r[lane] = a;
+    if (nh == 65) {
+        const double x63 = __shfl(a, 63, 64);
+        if (lane == 0) r[64] = (r[64] - F.link0[64] * x63) * F.invd0[64];
+    }
+}
+
+// Coupling of the chain heads of the two elements adjacent to hat h:
+// sum_{(e,pi) adjacent} C[(pi,e)][h] * heads[pi n + e].
+__device__ __forceinline__ double head_coupling(const double* C, const double* heads, int bc, int n, int h) {
+    const int v = voh(bc, h);
+    double acc = 0.0;
+    if (v >= 1) {
+        const int q = v - 1;
+        acc += C[4 * q + 1] * heads[q] + C[4 * q + 3] * heads[n + q];
+    }
+    if (v <= n - 1) {
+        const int q = v;
+        acc += C[4 * q + 0] * heads[q] + C[4 * q + 2] * heads[n + q];
+    }
+    return acc;
+}
+
+template <typename TIN, typename TOUT, int CL, int MODE, bool COL, bool UNI>
+__global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, SweepArgs a) {
+    extern __shared__ double sm[];
+    const int n = d.n, p = d.p, nh = d.nh;
+    const int hs = nh + 1;
+    // LDS: per line A, B (hats), H1, H2 (chain heads); then staged hat factors
+    double* sA = sm;
+    double* sB = sA + 8 * hs;
+    double* sH1 = sB + 8 * hs;
+    double* sH2 = sH1 + 16 * n;
+    double* fbase = sH2 + 16 * n;
+    HatF FS, FM;
+    FS.invd0 = fbase;
+    FS.d0 = FS.invd0 + hs;
+    FS.link0 = FS.d0 + hs;
+    FS.cpl = FS.link0 + hs;
+    FM.invd0 = FS.cpl + 4 * n;
+    FM.d0 = FM.invd0 + hs;
+    FM.link0 = FM.d0 + hs;
+    FM.cpl = FM.link0 + hs;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nwaves = blockDim.x >> 6;
+    int c, l;
+    if (COL) {
+        c = wave * 8 + (lane >> 3);
+        l = lane & 7;
+    } else {
+        c = wave * 8 + (lane & 7);
+        l = lane >> 3;
+    }
+    const FactorLayout& fl = a.fl;
+    const double* S = a.facS;
+    const double* Mf = a.facM;
+    const bool useS = (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE);
+
+    // ---- stage the hat factors
+    for (int i = tid; i < hs; i += blockDim.x) {
+        const bool inr = i < nh;
+        if (useS) {
+            FS.invd0[i] = inr ? S[fl.off_invd0 + i] : 0.0;
+            FS.d0[i] = inr ? S[fl.off_d0 + i] : 0.0;
+            FS.link0[i] = inr ? S[fl.off_link0 + i] : 0.0;
+        }
+        FM.invd0[i] = inr ? Mf[fl.off_invd0 + i] : 0.0;
+        FM.d0[i] = inr ? Mf[fl.off_d0 + i] : 0.0;
+        FM.link0[i] = inr ? Mf[fl.off_link0 + i] : 0.0;
+    }
+    for (int i = tid; i < 4 * n; i += blockDim.x) {
+        if (useS) FS.cpl[i] = S[fl.off_cpl + i];
+        FM.cpl[i] = Mf[fl.off_cpl + i];
+    }
+
+    auto line_of = [&](int ll) -> int {
+        const int lint = blockIdx.x * 8 + ll;
+        if (lint < a.nh_lines) return lint;
+        if (lint < a.hpad_lines) return -1;
+        return lint - (a.hpad_lines - a.nh_lines);
+    };
+    const int line = line_of(l);
+    const bool lact = line >= 0 && line < a.nlines;
+    const bool act = lact && c < 2 * n;
+    // On a uniform mesh with n % 8 == 0 the 8 chains of a wavefront share their parity,
+    // so degree-dependent coefficients are wavefront-uniform (scalar loads).
+    const int pi = UNI ? __builtin_amdgcn_readfirstlane(c >= n ? 1 : 0) : (c >= n ? 1 : 0);
+    const int e = c - pi * n;
+    const int len = pi ? (p - 1) / 2 : p / 2;
+
+    double* A = sA + l * hs;
+    double* B = sB + l * hs;
+    double* H1 = sH1 + l * 2 * n;
+    double* H2 = sH2 + l * 2 * n;
+
+    // per-degree coefficients (App. A entries and factor entries at degree m)
+    const double* kd = d.tab64;
+    const double* md = d.tab64 + d.tabstride;
+    const double* mo = d.tab64 + 2 * d.tabstride;
+    const double de = d.delta[e < n ? e : 0], ide = d.invdelta[e < n ? e : 0];
+    const double* cf = a.coef;
+    auto S_inv = [&](int m) { return UNI ? cf[m * 8 + 0] : S[fl.off_invd + m * n + e]; };
+    auto S_lnk = [&](int m) { return UNI ? cf[m * 8 + 1] : S[fl.off_link + m * n + e]; };
+    auto M_d = [&](int m) { return UNI ? cf[m * 8 + 2] : Mf[fl.off_d + m * n + e]; };
+    auto M_lnk = [&](int m) { return UNI ? cf[m * 8 + 3] : Mf[fl.off_link + m * n + e]; };
+    auto M_inv = [&](int m) { return UNI ? cf[m * 8 + 4] : Mf[fl.off_invd + m * n + e]; };
+    auto K_dg = [&](int m) { return UNI ? cf[m * 8 + 5] : kd[m] * ide; };
+    auto M_dg = [&](int m) { return UNI ? cf[m * 8 + 6] : md[m] * de; };
+    auto M_of = [&](int m) { return UNI ? cf[m * 8 + 7] : mo[m] * de; };
+
+    // addresses: chain step s of this thread sits at offset o + s * st (uniform meshes,
+    // n % 8 == 0: the layouts map a chain step to a constant stride); general case per step
+    auto IDX = [&](const Layout& L, int ln, int pos) -> long { return COL ? addr(L, pos, ln) : addr(L, ln, pos); };
+    auto chain_off = [&](const Layout& L, int s) -> long {
+        return IDX(L, line, nh + 2 * s * n + c);
+    };
+    const TIN* in = reinterpret_cast<const TIN*>(a.in);
+    long oi = 0, si = 0;
+    if (act) {
+        oi = chain_off(a.lin, 0);
+        si = UNI ? chain_off(a.lin, 1) - oi : 0;
+    }
+    auto in_at = [&](int s) -> long { return UNI ? oi + s * si : chain_off(a.lin, s); };
+
+    double y[CL];
+    if (act) {
+#pragma unroll
+        for (int s = 0; s < CL; ++s)
+            if (s < len) y[s] = (double)in[in_at(s)];
+        if (c < nh) A[c] = (double)in[IDX(a.lin, line, c)];
+    }
+
+    // The scanning wavefront of a line: wave w handles lines w, w + nwaves, ...
+    auto for_my_lines = [&](auto&& body) {
+        for (int ll = wave; ll < 8; ll += nwaves) {
+            const int ln = line_of(ll);
+            if (ln >= 0 && ln < a.nlines) body(ll);
+        }
+    };
+
+    if (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE) {
+        // ---- z = Lm^T y and the back substitution of S^{-1} z, fused (highest degree first)
+        if (act) {
+            double yo_next = 0.0, yp_next = 0.0;
+#pragma unroll
+            for (int s = CL - 1; s >= 0; --s) {
+                if (s < len) {
+                    const int m = pi + 2 * s;
+                    const double yo = y[s];
+                    double z = M_d(m) * yo;
+                    double v = 0.0;
+                    if (s + 1 < CL) {
+                        if (s + 1 < len) {
+                            z += M_lnk(m + 2) * yo_next;
+                            v = S_lnk(m + 2) * yp_next;
+                        }
+                    }
+                    const double yp = (z - v) * S_inv(m);
+                    y[s] = yp;
+                    yo_next = yo;
+                    yp_next = yp;
+                }
+            }
+            H1[c] = len > 0 ? yo_next : 0.0;  // heads of y
+            H2[c] = len > 0 ? yp_next : 0.0;  // heads of L_S^{-T} z
+        }
+        __syncthreads();
+        // ---- hats of z, right-hand side of the hat block of S, and its solve
+        for_my_lines([&](int ll) {
+            double* A2 = sA + ll * hs;
+            const double* h1 = sH1 + ll * 2 * n;
+            const double* h2 = sH2 + ll * 2 * n;
+            for (int h = lane; h < nh; h += 64) {
+                const double z = FM.d0[h] * A2[h] + FM.link0[h + 1] * (h + 1 < nh ? A2[h + 1] : 0.0) +
+                                 head_coupling(FM.cpl, h1, d.bc, n, h);
+                sB[ll * hs + h] = z - head_coupling(FS.cpl, h2, d.bc, n, h);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int h = lane; h < nh; h += 64) A2[h] = sB[ll * hs + h];
+            __builtin_amdgcn_wave_barrier();
+            hat_backward(A2, FS, nh, lane);
+            __builtin_amdgcn_wave_barrier();
+            hat_forward(A2, FS, nh, lane);
+        });
+        __syncthreads();
+        // ---- forward substitution x = L_S^{-1} (y' - C x_h) (lowest degree first)
+        double xl = 0.0, xr = 0.0;
+        if (act) {
+            if (vhat(d.bc, n, e)) xl = A[hov(d.bc, e)];
+            if (vhat(d.bc, n, e + 1)) xr = A[hov(d.bc, e + 1)];
+            double prev = 0.0;
+#pragma unroll
+            for (int s = 0; s < CL; ++s) {
+                if (s < len) {
+                    const int m = pi + 2 * s;
+                    double v = y[s];
+                    if (s == 0) v -= FS.cpl[4 * e + 2 * pi] * xl + FS.cpl[4 * e + 2 * pi + 1] * xr;
+                    else v -= S_lnk(m) * prev;
+                    prev = v * S_inv(m);
+                    y[s] = prev;
+                }
+            }
+            H1[c] = len > 0 ? y[0] : 0.0;  // heads of x
+        }
+        if (MODE == SWEEP_SOLVE) {
+            TOUT* out = reinterpret_cast<TOUT*>(a.out);
+            if (act) {
+                long oo = chain_off(a.lout, 0);
+                const long so = UNI ? chain_off(a.lout, 1) - oo : 0;
+#pragma unroll
+                for (int s = 0; s < CL; ++s)
+                    if (s < len) out[UNI ? oo + s * so : chain_off(a.lout, s)] = (TOUT)y[s];
+                if (c < nh) out[IDX(a.lout, line, c)] = (TOUT)A[c];
+            }
+            return;
+        }
+        // ---- product v = (kappa K + tau M) x and u = Lm^{-T} v, fused (highest degree first)
+        const double kap = a.kappa, tau = a.tau;
+        if (act) {
+            double x_next = 0.0, u_next = 0.0;
+#pragma unroll
+            for (int s = CL - 1; s >= 0; --s) {
+                if (s < len) {
+                    const int m = pi + 2 * s;
+                    const double x = y[s];
+                    double v = (kap * K_dg(m) + tau * M_dg(m)) * x;
+                    double w = 0.0;
+                    if (s > 0) v += tau * M_of(m - 2) * y[s - 1];
+                    if (s + 1 < CL) {
+                        if (s + 1 < len) {
+                            v += tau * M_of(m) * x_next;
+                            w = M_lnk(m + 2) * u_next;
+                        }
+                    }
+                    if (s == 0) v += pi == 0 ? (tau * de) * (xl + xr) * (1.0 / 6.0) : (tau * de) * (xr - xl) * (1.0 / 30.0);
+                    const double u = (v - w) * M_inv(m);
+                    y[s] = u;
+                    x_next = x;
+                    u_next = u;
+                }
+            }
+            H2[c] = len > 0 ? u_next : 0.0;  // heads of u
+        }
+        __syncthreads();
+        // ---- hat rows of the product, right-hand side of the Lm^T hat block, its solve
+        for_my_lines([&](int ll) {
+            double* A2 = sA + ll * hs;
+            double* B2 = sB + ll * hs;
+            const double* hx = sH1 + ll * 2 * n;
+            const double* hu = sH2 + ll * 2 * n;
+            for (int h = lane; h < nh; h += 64) {
+                const int v = voh(d.bc, h);
+                const double xh = A2[h];
+                double r = 0.0;
+                if (v >= 1) {
+                    const int q = v - 1;
+                    const double dq = d.delta[q], idq = d.invdelta[q];
+                    r += (kap * idq + tau * dq * (1.0 / 3.0)) * xh;
+                    if (vhat(d.bc, n, v - 1)) r += (-kap * idq + tau * dq * (1.0 / 6.0)) * A2[h - 1];
+                    r += tau * dq * (hx[q] * (1.0 / 6.0) + hx[n + q] * (1.0 / 30.0));
+                }
+                if (v <= n - 1) {
+                    const int q = v;
+                    const double dq = d.delta[q], idq = d.invdelta[q];
+                    r += (kap * idq + tau * dq * (1.0 / 3.0)) * xh;
+                    if (vhat(d.bc, n, v + 1)) r += (-kap * idq + tau * dq * (1.0 / 6.0)) * A2[h + 1];
+                    r += tau * dq * (hx[q] * (1.0 / 6.0) - hx[n + q] * (1.0 / 30.0));
+                }
+                B2[h] = r - head_coupling(FM.cpl, hu, d.bc, n, h);
+            }
+            __builtin_amdgcn_wave_barrier();
+            hat_backward(B2, FM, nh, lane);
+        });
+        __syncthreads();
+        const TIN* g = reinterpret_cast<const TIN*>(a.g);
+        TOUT* out = reinterpret_cast<TOUT*>(a.out);
+        if (act) {
+            const long og = chain_off(a.lg, 0), oo = chain_off(a.lout, 0);
+            const long sg = UNI ? chain_off(a.lg, 1) - og : 0, so = UNI ? chain_off(a.lout, 1) - oo : 0;
+#pragma unroll
+            for (int s = 0; s < CL; ++s)
+                if (s < len) {
+                    const long ig = UNI ? og + s * sg : chain_off(a.lg, s);
+                    const long io = UNI ? oo + s * so : chain_off(a.lout, s);
+                    out[io] = (TOUT)((double)g[ig] - y[s]);
+                }
+            if (c < nh) out[IDX(a.lout, line, c)] = (TOUT)((double)g[IDX(a.lg, line, c)] - B[c]);
+        }
+        return;
+    }
+
+    if (MODE == SWEEP_TRANSFORM) {
+        // ---- u = Lm^{-T} y: chain back substitution, then the hat block
+        if (act) {
+            double u_next = 0.0;
+#pragma unroll
+            for (int s = CL - 1; s >= 0; --s) {
+                if (s < len) {
+                    const int m = pi + 2 * s;
+                    double v = y[s];
+                    if (s + 1 < CL) {
+                        if (s + 1 < len) v -= M_lnk(m + 2) * u_next;
+                    }
+                    u_next = v * M_inv(m);
+                    y[s] = u_next;
+                }
+            }
+            H2[c] = len > 0 ? y[0] : 0.0;
+        }
+        __syncthreads();
+        for_my_lines([&](int ll) {
+            double* A2 = sA + ll * hs;
+            const double* hu = sH2 + ll * 2 * n;
+            for (int h = lane; h < nh; h += 64) A2[h] -= head_coupling(FM.cpl, hu, d.bc, n, h);
+            __builtin_amdgcn_wave_barrier();
+            hat_backward(A2, FM, nh, lane);
+        });
+        __syncthreads();
+        TOUT* out = reinterpret_cast<TOUT*>(a.out);
+        if (act) {
+            const long oo = chain_off(a.lout, 0);
+            const long so = UNI ? chain_off(a.lout, 1) - oo : 0;
+#pragma unroll
+            for (int s = 0; s < CL; ++s)
+                if (s < len) out[UNI ? oo + s * so : chain_off(a.lout, s)] = (TOUT)y[s];
+            if (c < nh) out[IDX(a.lout, line, c)] = (TOUT)A[c];
+        }
+        return;
+    }
+
+    if (MODE == SWEEP_FINAL) {
+        // ---- u = Lm^{-1} w: hat block first (forward), then the chains (lowest degree first)
+        __syncthreads();
+        for_my_lines([&](int ll) { hat_forward(sA + ll * hs, FM, nh, lane); });
+        __syncthreads();
+        double sdx = 0.0, su = 0.0;
+        if (act) {
+            double xl = 0.0, xr = 0.0;
+            if (vhat(d.bc, n, e)) xl = A[hov(d.bc, e)];
+            if (vhat(d.bc, n, e + 1)) xr = A[hov(d.bc, e + 1)];
+            double* out = reinterpret_cast<double*>(a.out);
+            const double* w = d.mdiag;
+            double prev = 0.0;
+#pragma unroll
+            for (int s = 0; s < CL; ++s) {
+                if (s < len) {
+                    const int m = pi + 2 * s;
+                    double v = y[s];
+                    if (s == 0) v -= FM.cpl[4 * e + 2 * pi] * xl + FM.cpl[4 * e + 2 * pi + 1] * xr;
+                    else v -= M_lnk(m) * prev;
+                    prev = v * M_inv(m);
+                    const int pos = nh + 2 * s * n + c;
+                    const long o = chain_off(a.lout, s);
+                    const double u = a.accumulate ? out[o] + prev : prev;
+                    out[o] = u;
+                    sdx += w[pos] * prev * prev;
+                    su += w[pos] * u * u;
+                }
+            }
+            if (c < nh) {
+                const long o = IDX(a.lout, line, c);
+                const double dx = A[c];
+                const double u = a.accumulate ? out[o] + dx : dx;
+                out[o] = u;
+                sdx += w[c] * dx * dx;
+                su += w[c] * u * u;
+            }
+            if (a.norm_acc) {
+                const double wl = a.wline[line];
+                sdx *= wl;
+                su *= wl;
+            }
+        }
+        if (a.norm_acc) {
+            __syncthreads();
+            sm[2 * tid] = sdx;
+            sm[2 * tid + 1] = su;
+            __syncthreads();
+            for (int w2 = blockDim.x; w2 > 1; w2 = (w2 + 1) / 2) {
+                const int half = (w2 + 1) / 2;
+                if (tid + half < w2) {
+                    sm[2 * tid] += sm[2 * (tid + half)];
+                    sm[2 * tid + 1] += sm[2 * (tid + half) + 1];
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                atomicAdd(a.norm_acc + 0, sm[0]);
+                atomicAdd(a.norm_acc + 1, sm[1]);
+            }
+        }
+    }
+}
+
+// Per-degree coefficient records of a uniform mesh (see internal.h).
+__global__ void coef_kernel(DimDev d, const double* facS, int stride, const double* facM, FactorLayout fl, double* out) {
+    const int f = blockIdx.x;
+    const int n = d.n, p = d.p;
+    const double* S = facS + (size_t)f * stride;
+    const double de = d.delta[0], ide = d.invdelta[0];
+    for (int m = threadIdx.x; m < p - 1; m += blockDim.x) {
+        double* r = out + ((size_t)f * (p - 1) + m) * 8;
+        r[0] = S[fl.off_invd + m * n];
+        r[1] = S[fl.off_link + m * n];
+        r[2] = facM[fl.off_d + m * n];
+        r[3] = facM[fl.off_link + m * n];
+        r[4] = facM[fl.off_invd + m * n];
+        r[5] = d.tab64[m] * ide;
+        r[6] = d.tab64[d.tabstride + m] * de;
+        r[7] = d.tab64[2 * d.tabstride + m] * de;
+    }
+}
+
+size_t sweep_lds_bytes(const DimDev& d, int threads, int mode) {
+    const int hs = d.nh + 1;
+    size_t words = (size_t)8 * (2 * hs + 4 * d.n) + 2 * (3 * hs + 4 * d.n);
+    if (mode == SWEEP_FINAL && words < (size_t)threads * 2) words = (size_t)threads * 2;
+    return words * sizeof(double);
+}
+
+template <typename TIN, typename TOUT, int CL, int MODE, bool COL>
+hipError_t launch_s(const DimDev& d, const SweepArgs& a, hipStream_t s) {
+    const int threads = 64 * ((2 * d.n + 7) / 8);
+    if (threads > sweep_max_threads(CL) || d.nh > 65) return hipErrorInvalidValue;
+    const int blocks = (a.hpad_lines + a.nlines - a.nh_lines + 7) / 8;
+    const size_t lds = sweep_lds_bytes(d, threads, MODE);
+    if (a.coef && d.n % 8 == 0)
+        hipLaunchKernelGGL((sweep_kernel<TIN, TOUT, CL, MODE, COL, true>), dim3(blocks), dim3(threads), lds, s, d, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<TIN, TOUT, CL, MODE, COL, false>), dim3(blocks), dim3(threads), lds, s, d, a);
+    return hipGetLastError();
+}
+
+template <typename TIN, typename TOUT, int MODE>
+hipError_t by_cl(const DimDev& d, const SweepArgs& a, bool col, hipStream_t s) {
+    const int need = d.p / 2;
+#define HPADI_CASE(CLV)                                                                                   \
+    if (need <= CLV)                                                                                      \
+        return col ? launch_s<TIN, TOUT, CLV, MODE, true>(d, a, s) : launch_s<TIN, TOUT, CLV, MODE, false>(d, a, s);
+    HPADI_CASE(4)
+    HPADI_CASE(8)
+    HPADI_CASE(16)
+    HPADI_CASE(32)
+    HPADI_CASE(64)
+#undef HPADI_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
+                        hipStream_t s) {
+    if (a.nlines <= 0) return hipSuccess;
+    switch (mode) {
+        case SWEEP_FULL:
+            if (tin == 4 && tout == 4) return by_cl<float, float, SWEEP_FULL>(d, a, column, s);
+            if (tin == 8 && tout == 8) return by_cl<double, double, SWEEP_FULL>(d, a, column, s);
+            break;
+        case SWEEP_SOLVE:
+            if (tin == 4 && tout == 4) return by_cl<float, float, SWEEP_SOLVE>(d, a, column, s);
+            if (tin == 8 && tout == 8) return by_cl<double, double, SWEEP_SOLVE>(d, a, column, s);
+            break;
+        case SWEEP_TRANSFORM:
+            if (tin == 8 && tout == 8) return by_cl<double, double, SWEEP_TRANSFORM>(d, a, column, s);
+            if (tin == 8 && tout == 4) return by_cl<double, float, SWEEP_TRANSFORM>(d, a, column, s);
+            break;
+        case SWEEP_FINAL:
+            if (tin == 4 && tout == 8) return by_cl<float, double, SWEEP_FINAL>(d, a, column, s);
+            if (tin == 8 && tout == 8) return by_cl<double, double, SWEEP_FINAL>(d, a, column, s);
+            break;
+        default:
+            break;
+    }
+    return hipErrorInvalidValue;
+}
+
+int sweep_threads(int n) { return 64 * ((2 * n + 7) / 8); }
+
+hipError_t launch_coef_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
+                              FactorLayout fl, double* out, hipStream_t s) {
+    if (nf <= 0 || d.p < 2) return hipSuccess;
+    hipLaunchKernelGGL(coef_kernel, dim3(nf), dim3(64), 0, s, d, facS, stride, facM, fl, out);
+    return hipGetLastError();
+}
+
+}  // namespace hpadi

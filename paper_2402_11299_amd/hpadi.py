@@ -58,6 +58,8 @@ SIGNATURES = {
                                    ctypes.POINTER(hpadi_stats)]),
     "hpadi_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "hpadi_plan_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_plan_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "hpadi_plan_timing_read": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, _c_int_p]),
     "hpadi_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 
@@ -216,6 +218,18 @@ def hpadi_apply(plan, U, Y):
 
 def hpadi_plan_destroy(plan):
     lib().hpadi_plan_destroy(plan)
+
+
+def hpadi_plan_timing(plan, enable):
+    check(lib().hpadi_plan_timing(plan, int(bool(enable))), "hpadi_plan_timing")
+
+
+def hpadi_plan_timing_read(plan):
+    ms = (ctypes.c_double * 3)()
+    by = (ctypes.c_double * 3)()
+    ct = (ctypes.c_int * 3)()
+    check(lib().hpadi_plan_timing_read(plan, ms, by, ct), "hpadi_plan_timing_read")
+    return list(ms), list(by), list(ct)
 
 
 def hpadi_strerror(status):
