@@ -77,10 +77,9 @@ typedef struct {
 typedef struct {
     double inner_tol;   /* mixed mode: tolerance of each FP32 ADI solve (0 = 1e-5) */
     int max_rounds;     /* mixed mode: refinement round limit (0 = 8) */
-    int lines_col;      /* column pass: lines per workgroup (0 = automatic) */
-    int lines_row;      /* row pass: lines per workgroup (0 = automatic) */
+    int lines_per_block; /* half-sweep workgroup width, 4 or 8 lines (0 = automatic) */
     int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
-    int reserved[3];
+    int reserved[4];
 } hpadi_options;
 
 /* ---- 1D operators (Sec. 2, Sec. 3.1, App. A) -------------------------- */

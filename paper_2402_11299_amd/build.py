@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhpadi.so")
 
-SOURCES = ["host.cpp", "kernels.hip", "sweep.hip"]
+SOURCES = ["host.cpp", "kernels.hip", "sweep.hip", "sweep_uni.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -625,7 +625,9 @@ hpadi::SweepArgs sweep_args(const hpadi_plan_s* P, bool column, int j) {
     a.fl = fl;
     a.facS = fac + (size_t)j * fl.stride;
     a.facM = fac + (size_t)P->J * fl.stride;
-    a.coef = coef ? coef + (size_t)j * (D.op.p - 1) * 8 : nullptr;
+    a.coef = coef ? coef + (size_t)j * D.op.p * 8 : nullptr;
+    a.lpb = P->lint.panel;
+    a.idx32 = P->nint < (size_t(1) << 31) ? 1 : 0;
     return a;
 }
 
@@ -635,6 +637,7 @@ int transform_rhs(hpadi_plan_s* P, const double* R, long ldr, int ts) {
     hpadi::SweepArgs c = sweep_args(P, true, P->J);
     c.in = R;
     c.lin = user_layout(P, ldr);
+    if ((double)ldr * P->dx.op.N >= 2147483648.0) c.idx32 = 0;
     c.out = P->T64;
     c.lout = P->lint;
     int rc = timed_sweep(P, true, c, hpadi::SWEEP_TRANSFORM, 8, 8, 2, dofs * 16.0);
@@ -684,6 +687,7 @@ int run_adi(hpadi_plan_s* P, int ts, double* U, long ldu, bool accumulate) {
     f.lin = L;
     f.out = U;
     f.lout = user_layout(P, ldu);
+    if ((double)ldu * P->dx.op.N >= 2147483648.0) f.idx32 = 0;
     f.accumulate = accumulate ? 1 : 0;
     f.norm_acc = accumulate ? P->acc : nullptr;
     f.wline = P->dx.dev.mdiag;
@@ -901,7 +905,7 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     // per-degree coefficient records for the uniform-mesh fast path
     auto tables = [&](DimHost& D, double* fac, const FactorLayout& fl, double** out) -> int {
         if (!D.uniform || D.op.p < 2) return HPADI_OK;
-        if (dmalloc(out, (size_t)(J + 1) * (D.op.p - 1) * 8) != hipSuccess) return HPADI_ENOMEM;
+        if (dmalloc(out, (size_t)(J + 1) * D.op.p * 8) != hipSuccess) return HPADI_ENOMEM;
         return hpadi::launch_coef_tables(D.dev, J + 1, fac, fl.stride, fac + (size_t)J * fl.stride, fl, *out,
                                          P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
     };
@@ -912,13 +916,17 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     const int Nx = x->N, Ny = y->N;
     P->ldw = ((long)Ny + 63) / 64 * 64;
     hpadi::Layout& L = P->lint;
-    L.panel = 1;
+    // 4-line workgroups (two per compute unit) when both axes allow the uniform fast path
+    // with 16 chains per wavefront; 8-line workgroups otherwise.
+    const int pw = P->opt.lines_per_block == 8 ? 8
+                   : (P->opt.lines_per_block == 4 || (x->n % 16 == 0 && y->n % 16 == 0)) ? 4 : 8;
+    L.panel = pw;
     L.nhr = x->nh;
     L.nhc = y->nh;
     L.offr = P->dx.hpad - x->nh;
     L.offc = P->dy.hpad - y->nh;
-    L.ld = (long)P->dx.Npad * 8;
-    const long panels = (P->dy.Npad + 7) / 8;
+    L.ld = (long)P->dx.Npad * pw;
+    const long panels = (P->dy.Npad + pw - 1) / pw;
     P->nint = (size_t)panels * L.ld;
     const size_t ts = precision == HPADI_FP64 ? 8 : 4;
     bool ok = hipMalloc(&P->Wk, P->nint * ts) == hipSuccess && hipMalloc(&P->Gt, P->nint * ts) == hipSuccess &&

@@ -59,11 +59,11 @@ hipError_t launch_factor(const DimDev& d, int nf, const double* kappa_dev, const
                          double* fac64, float* fac32, int stride, int* status_dev, hipStream_t s);
 
 // Entry (i, j) of an Nx x Ny array: row-major (ptr[i*ld + j]) or the internal
-// 8-column panel layout (panel j/8 at offset (j/8)*ld, row i at 8 i within it),
+// panel layout of width w (panel j/w at offset (j/w)*ld, row i at w i within it),
 // with row/column indices past the hats shifted by offr/offc (alignment padding).
 struct Layout {
     long ld;
-    int panel;
+    int panel;       // 0 row-major; else the panel width (4 or 8 columns)
     int nhr, nhc;    // hats along x (rows) and y (columns)
     int offr, offc;  // padding shift of indices >= nhr / >= nhc
 };
@@ -82,18 +82,27 @@ struct SweepArgs {
     int nlines;                     // lines of the problem
     int nh_lines, hpad_lines;       // hats along the line index, and their padded count
     int accumulate;                 // FINAL: U += u (1) or U = u (0)
+    int lpb;                        // lines per workgroup: the panel width of the internal layout (4 or 8)
+    int idx32;                      // every array addressed by this sweep has < 2^31 entries
     double* norm_acc;               // FINAL: [sum w u^2, sum w U^2] or NULL
     const double* wline;            // FINAL: weight per line
 };
 hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
                         hipStream_t s);
 // Per-degree coefficient records for a uniform mesh, for nf shifted factors (records f * stride of
-// facS) each paired with the mass factor facM: out[(f (p-1) + m) * 8 + k] =
+// facS) each paired with the mass factor facM: out[(f p + m) * 8 + k] =
 //   S.invd, S.link, M.d, M.link, M.invd (at degree m, element 0), 4/((2m+3) delta),
-//   2 delta/((2m+1)(2m+3)(2m+5)), -delta/((2m+3)(2m+5)(2m+7)).
+//   2 delta/((2m+1)(2m+3)(2m+5)), -delta/((2m+3)(2m+5)(2m+7)),
+// for m = 0..p-2, and a zero record at m = p-1 (a phantom degree that pads a chain
+// one short of the compile-time chain length).
 hipError_t launch_coef_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
                               FactorLayout fl, double* out, hipStream_t s);
-int sweep_threads(int n);
+int sweep_threads(int n, int lines_per_block);
+// Uniform-mesh fast path (sweep_uni.hip): usable when the mesh is uniform (coef != NULL),
+// n is a multiple of the chains per wavefront and p/2 is one of 4, 8, 16, 32, 64.
+bool sweep_uni_available(const DimDev& d, int lines_per_block);
+hipError_t launch_sweep_uni(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
+                            hipStream_t s);
 
 // Banded operator along lines, elementwise: out = (kappa K + tau M) x per line
 // (and optionally a second output with (kappa2, tau2)).  FP64.

@@ -14,12 +14,12 @@
 // live in FP32 without the mass matrix amplifying the rounding.  All arithmetic
 // here is FP64 (registers are not the bottleneck of a bandwidth-bound sweep).
 //
-// Work decomposition: a workgroup owns 8 lines (one 8-wide panel of the internal
-// layout) and one thread owns one bubble chain (element e, parity pi) of one
-// line, kept in registers.  Chain c = pi n + e of a line holds positions
+// Work decomposition: a workgroup owns LW = 4 or 8 lines (one panel of the
+// internal layout) and one thread owns one bubble chain (element e, parity pi)
+// of one line, kept in registers.  Chain c = pi n + e of a line holds positions
 // nh + 2 s n + c, s = 0, 1, ..., so the 2n chains of a step are consecutive and
-// each wavefront reads 8 lines x 8 consecutive positions: 256 contiguous bytes
-// (FP32) in both sweep directions.  The hat block of each line (the Schur
+// each wavefront reads LW lines x 64/LW consecutive positions: 256 bytes (FP32)
+// in contiguous runs of at least 64 bytes, in both sweep directions.  The hat block of each line (the Schur
 // complement of Alg. 1, n_h <= 65 unknowns) is solved by one wavefront per line
 // as parallel prefix/suffix scans of affine maps, with the hat factors staged in
 // LDS.
@@ -27,122 +27,28 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "sweep_common.h"
 
 namespace hpadi {
 
+using namespace sweep_detail;
+
 namespace {
 
-__device__ __forceinline__ bool vhat(int bc, int n, int v) { return bc == 0 ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n); }
-__device__ __forceinline__ int hov(int bc, int v) { return bc == 0 ? v - 1 : v; }
-__device__ __forceinline__ int voh(int bc, int h) { return bc == 0 ? h + 1 : h; }
-
-__device__ __forceinline__ long addr(const Layout& L, int i, int j) {
-    const int ii = i >= L.nhr ? i + L.offr : i;
-    const int jj = j >= L.nhc ? j + L.offc : j;
-    return L.panel ? (long)(jj >> 3) * L.ld + (long)ii * 8 + (jj & 7) : (long)ii * L.ld + jj;
-}
-
-constexpr int sweep_max_threads(int cl) { return cl <= 32 ? 1024 : 512; }
-
-// Staged hat data of one factor: 1/diag, diag, sub-diagonal of L0, coupling C.
-struct HatF {
-    double* invd0;
-    double* d0;
-    double* link0;  // link0[h] = L0[h][h-1]; link0[nh] = 0 (sentinel)
-    double* cpl;    // 4n
-};
-
-// Suffix scan over lanes of affine maps z = a + b z_next (lane k composes with
-// lane k+1, k+2, ...): afterwards a = value of the recurrence run from the last
-// lane down to k with terminal value 0.
-__device__ __forceinline__ void suffix_scan(double& a, double& b, int lane, int nl) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double a2 = __shfl_down(a, d, 64);
-        const double b2 = __shfl_down(b, d, 64);
-        if (lane + d < nl) {
-            a = a + b * a2;
-            b = b * b2;
-        }
-    }
-}
-// Prefix scan: x = a + b x_prev, composed with lanes k-1, k-2, ...
-__device__ __forceinline__ void prefix_scan(double& a, double& b, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double a2 = __shfl_up(a, d, 64);
-        const double b2 = __shfl_up(b, d, 64);
-        if (lane >= d) {
-            a = a + b * a2;
-            b = b * b2;
-        }
-    }
-}
-
-// Hat-block backward solve L0^T z = r for one line, by one full wavefront.
-// r: LDS hat array (nh <= 65), overwritten with z.  Lane k owns hat k; lane 63
-// also owns hat 64 when nh = 65.
-__device__ __forceinline__ void hat_backward(double* r, const HatF& F, int nh, int lane) {
-    const int nl = nh < 64 ? nh : 64;
-    double a = 0.0, b = 1.0;
-    double a64 = 0.0;
-    if (lane < nl) {
-        a = r[lane] * F.invd0[lane];
-        b = -F.link0[lane + 1] * F.invd0[lane];
-        if (lane == 63 && nh == 65) {
-            a64 = r[64] * F.invd0[64];
-            a = a + b * a64;  // compose with hat 64 (whose own map is constant)
-            b = 0.0;
-        }
-    }
-    suffix_scan(a, b, lane, nl);
-    if (lane < nl) r[lane] = a;
-    if (lane == 63 && nh == 65) r[64] = a64;
-}
-
-// Hat-block forward solve L0 x = z for one line (in place on r).
-__device__ __forceinline__ void hat_forward(double* r, const HatF& F, int nh, int lane) {
-    const int nl = nh < 64 ? nh : 64;
-    double a = 0.0, b = 0.0;
-    if (lane < nl) {
-        a = r[lane] * F.invd0[lane];
-        b = -F.link0[lane] * F.invd0[lane];
-    }
-    prefix_scan(a, b, lane);
-    if (lane < nl) r[lane] = a;
-    if (nh == 65) {
-        const double x63 = __shfl(a, 63, 64);
-        if (lane == 0) r[64] = (r[64] - F.link0[64] * x63) * F.invd0[64];
-    }
-}
-
-// Coupling of the chain heads of the two elements adjacent to hat h:
-// sum_{(e,pi) adjacent} C[(pi,e)][h] * heads[pi n + e].
-__device__ __forceinline__ double head_coupling(const double* C, const double* heads, int bc, int n, int h) {
-    const int v = voh(bc, h);
-    double acc = 0.0;
-    if (v >= 1) {
-        const int q = v - 1;
-        acc += C[4 * q + 1] * heads[q] + C[4 * q + 3] * heads[n + q];
-    }
-    if (v <= n - 1) {
-        const int q = v;
-        acc += C[4 * q + 0] * heads[q] + C[4 * q + 2] * heads[n + q];
-    }
-    return acc;
-}
-
-template <typename TIN, typename TOUT, int CL, int MODE, bool COL, bool UNI>
+template <typename TIN, typename TOUT, int CL, int MODE, bool COL, bool UNI, int LW>
 __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, SweepArgs a) {
+    // LW lines per workgroup (the panel width of the internal layout); CW chains per
+    // wavefront, so that a wavefront touches LW lines x CW consecutive positions.
+    constexpr int CW = 64 / LW;
     extern __shared__ double sm[];
     const int n = d.n, p = d.p, nh = d.nh;
     const int hs = nh + 1;
     // LDS: per line A, B (hats), H1, H2 (chain heads); then staged hat factors
     double* sA = sm;
-    double* sB = sA + 8 * hs;
-    double* sH1 = sB + 8 * hs;
-    double* sH2 = sH1 + 16 * n;
-    double* fbase = sH2 + 16 * n;
+    double* sB = sA + LW * hs;
+    double* sH1 = sB + LW * hs;
+    double* sH2 = sH1 + LW * 2 * n;
+    double* fbase = sH2 + LW * 2 * n;
     HatF FS, FM;
     FS.invd0 = fbase;
     FS.d0 = FS.invd0 + hs;
@@ -152,17 +58,18 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
     FM.d0 = FM.invd0 + hs;
     FM.link0 = FM.d0 + hs;
     FM.cpl = FM.link0 + hs;
+    double* scf = FM.cpl + 4 * n;  // uniform meshes: per-degree records, 8 (p-1) doubles
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int nwaves = blockDim.x >> 6;
     int c, l;
     if (COL) {
-        c = wave * 8 + (lane >> 3);
-        l = lane & 7;
+        c = wave * CW + lane / LW;
+        l = lane % LW;
     } else {
-        c = wave * 8 + (lane & 7);
-        l = lane >> 3;
+        c = wave * CW + lane % CW;
+        l = lane / CW;
     }
     const FactorLayout& fl = a.fl;
     const double* S = a.facS;
@@ -185,9 +92,11 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
         if (useS) FS.cpl[i] = S[fl.off_cpl + i];
         FM.cpl[i] = Mf[fl.off_cpl + i];
     }
+    if (UNI)
+        for (int i = tid; i < 8 * p; i += blockDim.x) scf[i] = a.coef[i];
 
     auto line_of = [&](int ll) -> int {
-        const int lint = blockIdx.x * 8 + ll;
+        const int lint = blockIdx.x * LW + ll;
         if (lint < a.nh_lines) return lint;
         if (lint < a.hpad_lines) return -1;
         return lint - (a.hpad_lines - a.nh_lines);
@@ -195,7 +104,7 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
     const int line = line_of(l);
     const bool lact = line >= 0 && line < a.nlines;
     const bool act = lact && c < 2 * n;
-    // On a uniform mesh with n % 8 == 0 the 8 chains of a wavefront share their parity,
+    // On a uniform mesh with n % CW == 0 the CW chains of a wavefront share their parity,
     // so degree-dependent coefficients are wavefront-uniform (scalar loads).
     const int pi = UNI ? __builtin_amdgcn_readfirstlane(c >= n ? 1 : 0) : (c >= n ? 1 : 0);
     const int e = c - pi * n;
@@ -211,7 +120,7 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
     const double* md = d.tab64 + d.tabstride;
     const double* mo = d.tab64 + 2 * d.tabstride;
     const double de = d.delta[e < n ? e : 0], ide = d.invdelta[e < n ? e : 0];
-    const double* cf = a.coef;
+    const double* cf = scf;
     auto S_inv = [&](int m) { return UNI ? cf[m * 8 + 0] : S[fl.off_invd + m * n + e]; };
     auto S_lnk = [&](int m) { return UNI ? cf[m * 8 + 1] : S[fl.off_link + m * n + e]; };
     auto M_d = [&](int m) { return UNI ? cf[m * 8 + 2] : Mf[fl.off_d + m * n + e]; };
@@ -242,10 +151,11 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
             if (s < len) y[s] = (double)in[in_at(s)];
         if (c < nh) A[c] = (double)in[IDX(a.lin, line, c)];
     }
+    if (UNI) __syncthreads();  // staged per-degree records
 
     // The scanning wavefront of a line: wave w handles lines w, w + nwaves, ...
     auto for_my_lines = [&](auto&& body) {
-        for (int ll = wave; ll < 8; ll += nwaves) {
+        for (int ll = wave; ll < LW; ll += nwaves) {
             const int ln = line_of(ll);
             if (ln >= 0 && ln < a.nlines) body(ll);
         }
@@ -511,8 +421,12 @@ __global__ void coef_kernel(DimDev d, const double* facS, int stride, const doub
     const int n = d.n, p = d.p;
     const double* S = facS + (size_t)f * stride;
     const double de = d.delta[0], ide = d.invdelta[0];
-    for (int m = threadIdx.x; m < p - 1; m += blockDim.x) {
-        double* r = out + ((size_t)f * (p - 1) + m) * 8;
+    for (int m = threadIdx.x; m < p; m += blockDim.x) {
+        double* r = out + ((size_t)f * p + m) * 8;
+        if (m == p - 1) {  // phantom degree p-1: zero coefficients make it inert in the recurrences
+            for (int k = 0; k < 8; ++k) r[k] = 0.0;
+            continue;
+        }
         r[0] = S[fl.off_invd + m * n];
         r[1] = S[fl.off_link + m * n];
         r[2] = facM[fl.off_d + m * n];
@@ -524,24 +438,23 @@ __global__ void coef_kernel(DimDev d, const double* facS, int stride, const doub
     }
 }
 
-size_t sweep_lds_bytes(const DimDev& d, int threads, int mode) {
-    const int hs = d.nh + 1;
-    size_t words = (size_t)8 * (2 * hs + 4 * d.n) + 2 * (3 * hs + 4 * d.n);
-    if (mode == SWEEP_FINAL && words < (size_t)threads * 2) words = (size_t)threads * 2;
-    return words * sizeof(double);
+template <typename TIN, typename TOUT, int CL, int MODE, bool COL, int LW>
+hipError_t launch_lw(const DimDev& d, const SweepArgs& a, hipStream_t s) {
+    constexpr int CW = 64 / LW;
+    const int threads = 64 * ((2 * d.n + CW - 1) / CW);
+    if (threads > sweep_max_threads(CL) || d.nh > 65) return hipErrorInvalidValue;
+    const int blocks = (a.hpad_lines + a.nlines - a.nh_lines + LW - 1) / LW;
+    const size_t lds = sweep_lds_bytes(d, threads, MODE);
+    if (a.coef && d.n % CW == 0)
+        hipLaunchKernelGGL((sweep_kernel<TIN, TOUT, CL, MODE, COL, true, LW>), dim3(blocks), dim3(threads), lds, s, d, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<TIN, TOUT, CL, MODE, COL, false, LW>), dim3(blocks), dim3(threads), lds, s, d, a);
+    return hipGetLastError();
 }
 
 template <typename TIN, typename TOUT, int CL, int MODE, bool COL>
 hipError_t launch_s(const DimDev& d, const SweepArgs& a, hipStream_t s) {
-    const int threads = 64 * ((2 * d.n + 7) / 8);
-    if (threads > sweep_max_threads(CL) || d.nh > 65) return hipErrorInvalidValue;
-    const int blocks = (a.hpad_lines + a.nlines - a.nh_lines + 7) / 8;
-    const size_t lds = sweep_lds_bytes(d, threads, MODE);
-    if (a.coef && d.n % 8 == 0)
-        hipLaunchKernelGGL((sweep_kernel<TIN, TOUT, CL, MODE, COL, true>), dim3(blocks), dim3(threads), lds, s, d, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<TIN, TOUT, CL, MODE, COL, false>), dim3(blocks), dim3(threads), lds, s, d, a);
-    return hipGetLastError();
+    return a.lpb == 4 ? launch_lw<TIN, TOUT, CL, MODE, COL, 4>(d, a, s) : launch_lw<TIN, TOUT, CL, MODE, COL, 8>(d, a, s);
 }
 
 template <typename TIN, typename TOUT, int MODE>
@@ -561,9 +474,20 @@ hipError_t by_cl(const DimDev& d, const SweepArgs& a, bool col, hipStream_t s) {
 
 }  // namespace
 
+namespace sweep_detail {
+size_t sweep_lds_bytes(const DimDev& d, int threads, int mode) {
+    const int hs = d.nh + 1;
+    size_t words = (size_t)8 * (2 * hs + 4 * d.n) + 2 * (3 * hs + 4 * d.n) + 8 * d.p;  // LW <= 8
+    if (mode == SWEEP_FINAL && words < (size_t)threads * 2) words = (size_t)threads * 2;
+    return words * sizeof(double);
+}
+
+}  // namespace sweep_detail
+
 hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
                         hipStream_t s) {
     if (a.nlines <= 0) return hipSuccess;
+    if (a.coef && a.idx32 && sweep_uni_available(d, a.lpb)) return launch_sweep_uni(d, a, mode, tin, tout, column, s);
     switch (mode) {
         case SWEEP_FULL:
             if (tin == 4 && tout == 4) return by_cl<float, float, SWEEP_FULL>(d, a, column, s);
@@ -587,7 +511,10 @@ hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, 
     return hipErrorInvalidValue;
 }
 
-int sweep_threads(int n) { return 64 * ((2 * n + 7) / 8); }
+int sweep_threads(int n, int lines_per_block) {
+    const int cw = 64 / lines_per_block;
+    return 64 * ((2 * n + cw - 1) / cw);
+}
 
 hipError_t launch_coef_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
                               FactorLayout fl, double* out, hipStream_t s) {

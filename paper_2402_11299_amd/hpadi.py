@@ -30,8 +30,8 @@ class hpadi_stats(ctypes.Structure):
 
 class hpadi_options(ctypes.Structure):
     _fields_ = [("inner_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
-                ("lines_col", ctypes.c_int), ("lines_row", ctypes.c_int),
-                ("fixed_rounds", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("lines_per_block", ctypes.c_int),
+                ("fixed_rounds", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 # name -> (restype, argtypes), in the order of include/hpadi.h
