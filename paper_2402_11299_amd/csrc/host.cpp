@@ -448,6 +448,8 @@ struct hpadi_plan_s {
     double* facy64 = nullptr;     // J+1 records: K_y + (w/2 + p_j) M_y, then M_y
     double* coefx = nullptr;      // uniform meshes: (J+1) (p_x-1) 8 per-degree coefficient records
     double* coefy = nullptr;
+    double* ptabx = nullptr;      // uniform meshes: J folded per-pass tables (p_x records of 16 doubles)
+    double* ptaby = nullptr;
     int* status = nullptr;
     // work arrays in the internal panel layout
     hpadi::Layout lint{};
@@ -566,6 +568,8 @@ void plan_free(hpadi_plan_s* P) {
     if (P->facy64) hipFree(P->facy64);
     if (P->coefy != P->coefx && P->coefx) hipFree(P->coefx);
     if (P->coefy) hipFree(P->coefy);
+    if (P->ptabx) hipFree(P->ptabx);
+    if (P->ptaby) hipFree(P->ptaby);
     for (void* q : {(void*)P->status, P->Wk, P->Gt, (void*)P->T64, (void*)P->T1, (void*)P->T2, (void*)P->R64,
                     (void*)P->H, (void*)P->acc})
         if (q) hipFree(q);
@@ -626,6 +630,8 @@ hpadi::SweepArgs sweep_args(const hpadi_plan_s* P, bool column, int j) {
     a.facS = fac + (size_t)j * fl.stride;
     a.facM = fac + (size_t)P->J * fl.stride;
     a.coef = coef ? coef + (size_t)j * D.op.p * 8 : nullptr;
+    const double* ptab = column ? P->ptabx : P->ptaby;
+    a.ptab = ptab ? ptab + (size_t)(j < P->J ? j : 0) * D.op.p * 16 : nullptr;
     a.lpb = P->lint.panel;
     a.idx32 = P->nint < (size_t(1) << 31) ? 1 : 0;
     return a;
@@ -912,6 +918,35 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     if ((rc = tables(P->dy, P->facy64, P->fly, &P->coefy)) != HPADI_OK) { plan_free(P); return rc; }
     if (shared) P->coefx = P->coefy;
     else if ((rc = tables(P->dx, P->facx64, P->flx, &P->coefx)) != HPADI_OK) { plan_free(P); return rc; }
+    // folded per-pass records: row pass j (S_y(w/2 + p_j), product tau = w/2 + q_j) and
+    // column pass j (S_x(w/2 - q_j), product tau = w/2 - p_{j+1}; none after the last)
+    auto ptables = [&](DimHost& D, double* fac, const FactorLayout& fl, const std::vector<double>& tau,
+                       double** out) -> int {
+        if (!D.uniform || D.op.p < 2) return HPADI_OK;
+        if (dmalloc(out, (size_t)J * D.op.p * 16) != hipSuccess) return HPADI_ENOMEM;
+        double* td = nullptr;
+        if (dmalloc(&td, J) != hipSuccess) return HPADI_ENOMEM;
+        int r = HPADI_OK;
+        if (hipMemcpyAsync(td, tau.data(), J * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+            hpadi::launch_pass_tables(D.dev, J, fac, fl.stride, fac + (size_t)J * fl.stride, fl, td, 1.0, *out,
+                                      P->stream) != hipSuccess ||
+            hipStreamSynchronize(P->stream) != hipSuccess)
+            r = HPADI_EHIP;
+        hipFree(td);
+        return r;
+    };
+    {
+        std::vector<double> tr(J), tc(J);
+        for (int j = 0; j < J; ++j) {
+            tr[j] = half + P->Q[j];
+            tc[j] = j + 1 < J ? half - P->P[j + 1] : 0.0;
+        }
+        if ((rc = ptables(P->dy, P->facy64, P->fly, tr, &P->ptaby)) != HPADI_OK ||
+            (rc = ptables(P->dx, P->facx64, P->flx, tc, &P->ptabx)) != HPADI_OK) {
+            plan_free(P);
+            return rc;
+        }
+    }
     // workspace: internal panel layout (8-column panels, hats padded to a multiple of 8)
     const int Nx = x->N, Ny = y->N;
     P->ldw = ((long)Ny + 63) / 64 * 64;

@@ -77,6 +77,7 @@ struct SweepArgs {
     const double* facS;             // factor of the shifted operator (FULL, SOLVE)
     const double* facM;             // factor of this direction's mass matrix
     const double* coef;             // uniform meshes: per-degree coefficient records (8 doubles per m), or NULL
+    const double* ptab;             // uniform meshes: folded per-pass records (16 doubles per m), or NULL
     FactorLayout fl;
     double kappa, tau;              // FULL: product kappa K + tau M
     int nlines;                     // lines of the problem
@@ -97,6 +98,16 @@ hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, 
 // one short of the compile-time chain length).
 hipError_t launch_coef_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
                               FactorLayout fl, double* out, hipStream_t s);
+// Folded per-pass records for the uniform-mesh kernel: for pass f (shifted factor f of
+// facS, product tau[f]), out[(f p + m) * 16 + k], m = 0..p-1 (m = p-1 a zero record):
+//   0 b1 = M.d(m) S.invd(m)        1 b2 = M.link(m+2) S.invd(m)    2 b3 = -S.link(m+2) S.invd(m)
+//   3 c1 = S.invd(m)               4 c2 = -S.link(m) S.invd(m)
+//   5 a1 = M.invd(m) (kappa K_mm + tau M_mm)   6 a2 = M.invd(m) tau M_{m-2,m}
+//   7 a3 = M.invd(m) tau M_{m,m+2}             8 a4 = -M.invd(m) M.link(m+2)
+//   9 f1 = M.invd(m)               10 f2 = -M.link(m) M.invd(m)   11 t2 = -M.link(m+2) M.invd(m)
+//   12 M.invd(m) tau delta (head term), 13..15 unused.
+hipError_t launch_pass_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
+                              FactorLayout fl, const double* tau_dev, double kappa, double* out, hipStream_t s);
 int sweep_threads(int n, int lines_per_block);
 // Uniform-mesh fast path (sweep_uni.hip): usable when the mesh is uniform (coef != NULL),
 // n is a multiple of the chains per wavefront and p/2 is one of 4, 8, 16, 32, 64.

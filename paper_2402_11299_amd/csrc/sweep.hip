@@ -487,7 +487,7 @@ size_t sweep_lds_bytes(const DimDev& d, int threads, int mode) {
 hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
                         hipStream_t s) {
     if (a.nlines <= 0) return hipSuccess;
-    if (a.coef && a.idx32 && sweep_uni_available(d, a.lpb)) return launch_sweep_uni(d, a, mode, tin, tout, column, s);
+    if (a.ptab && a.idx32 && sweep_uni_available(d, a.lpb)) return launch_sweep_uni(d, a, mode, tin, tout, column, s);
     switch (mode) {
         case SWEEP_FULL:
             if (tin == 4 && tout == 4) return by_cl<float, float, SWEEP_FULL>(d, a, column, s);
@@ -514,6 +514,51 @@ hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, 
 int sweep_threads(int n, int lines_per_block) {
     const int cw = 64 / lines_per_block;
     return 64 * ((2 * n + cw - 1) / cw);
+}
+
+namespace {
+__global__ void pass_table_kernel(DimDev d, const double* facS, int stride, const double* facM, FactorLayout fl,
+                                  const double* tau_dev, double kappa, double* out) {
+    const int f = blockIdx.x;
+    const int n = d.n, p = d.p;
+    const double* S = facS + (size_t)f * stride;
+    const double de = d.delta[0], ide = d.invdelta[0];
+    const double tau = tau_dev ? tau_dev[f] : 0.0;
+    const double* kd = d.tab64;
+    const double* md = d.tab64 + d.tabstride;
+    const double* mo = d.tab64 + 2 * d.tabstride;
+    for (int m = threadIdx.x; m < p; m += blockDim.x) {
+        double* r = out + ((size_t)f * p + m) * 16;
+        for (int k = 0; k < 16; ++k) r[k] = 0.0;
+        if (m > p - 2) continue;  // phantom degree p-1
+        const bool up = m + 2 <= p - 2;
+        const double sinv = S[fl.off_invd + m * n], minv = facM[fl.off_invd + m * n];
+        const double slnk_up = up ? S[fl.off_link + (m + 2) * n] : 0.0;
+        const double mlnk_up = up ? facM[fl.off_link + (m + 2) * n] : 0.0;
+        const double slnk = m >= 2 ? S[fl.off_link + m * n] : 0.0;
+        const double mlnk = m >= 2 ? facM[fl.off_link + m * n] : 0.0;
+        r[0] = facM[fl.off_d + m * n] * sinv;
+        r[1] = mlnk_up * sinv;
+        r[2] = -slnk_up * sinv;
+        r[3] = sinv;
+        r[4] = -slnk * sinv;
+        r[5] = minv * (kappa * kd[m] * ide + tau * md[m] * de);
+        r[6] = m >= 2 ? minv * tau * mo[m - 2] * de : 0.0;
+        r[7] = up ? minv * tau * mo[m] * de : 0.0;
+        r[8] = -minv * mlnk_up;
+        r[9] = minv;
+        r[10] = -mlnk * minv;
+        r[11] = -mlnk_up * minv;
+        r[12] = minv * tau * de;
+    }
+}
+}  // namespace
+
+hipError_t launch_pass_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
+                              FactorLayout fl, const double* tau_dev, double kappa, double* out, hipStream_t s) {
+    if (nf <= 0 || d.p < 2) return hipSuccess;
+    hipLaunchKernelGGL(pass_table_kernel, dim3(nf), dim3(64), 0, s, d, facS, stride, facM, fl, tau_dev, kappa, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_coef_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,

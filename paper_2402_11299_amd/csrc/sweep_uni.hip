@@ -89,30 +89,33 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
     const int pi = __builtin_amdgcn_readfirstlane(c >= n ? 1 : 0);
     const int e = c - pi * n;
     const bool full = (pi ? (p - 1) / 2 : p / 2) == CL;  // else the last step is the phantom degree
-    const cptr cf = (cptr)(a.coef);
-    auto CF = [&](int m, int k) -> double { return cf[m * 8 + k]; };
+    const cptr pt = (cptr)(a.ptab);
+    auto PT = [&](int m, int k) -> double { return pt[m * 16 + k]; };
 
     auto IDX = [&](const Layout& L, int ln, int pos) -> long { return COL ? addr(L, pos, ln) : addr(L, ln, pos); };
-    auto chain0 = [&](const Layout& L, int& o, int& st) {
+    // byte offset of chain step 0 and byte stride per step (32-bit: loads and stores
+    // address a uniform base plus a per-lane 32-bit offset)
+    auto chain0 = [&](const Layout& L, unsigned& o, unsigned& st, unsigned esz) {
         const long o0 = IDX(L, line, nh + c);
-        o = (int)o0;
-        st = (int)(IDX(L, line, nh + 2 * n + c) - o0);
+        o = (unsigned)(o0 * esz);
+        st = (unsigned)((IDX(L, line, nh + 2 * n + c) - o0) * esz);
     };
 
-    const TIN* in = reinterpret_cast<const TIN*>(a.in);
+    const char* inb = reinterpret_cast<const char*>(a.in);
     double y[CL];
     if (act) {
         // issued highest degree first: the first recurrence consumes them in that order
-        int o, st;
-        chain0(a.lin, o, st);
+        unsigned o, st;
+        chain0(a.lin, o, st, sizeof(TIN));
         o += (CL - 1) * st;
-        y[CL - 1] = full ? (double)in[o] : 0.0;
+        y[CL - 1] = full ? (double)*reinterpret_cast<const TIN*>(inb + o) : 0.0;
 #pragma unroll
         for (int s = CL - 2; s >= 0; --s) {
             o -= st;
-            y[s] = (double)in[o];
+            y[s] = (double)*reinterpret_cast<const TIN*>(inb + o);
         }
     }
+    const TIN* in = reinterpret_cast<const TIN*>(a.in);
     double* A = sA + l * hs;
     double* B = sB + l * hs;
     double* H1 = sH1 + l * 2 * n;
@@ -126,31 +129,28 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
         }
     };
     auto store_chain = [&](TOUT* out, const Layout& L, auto&& value) {
-        int o, st;
-        chain0(L, o, st);
+        unsigned o, st;
+        chain0(L, o, st, sizeof(TOUT));
+        char* ob = reinterpret_cast<char*>(out);
 #pragma unroll
         for (int s = 0; s < CL - 1; ++s) {
-            out[o] = (TOUT)value(s, o);
+            *reinterpret_cast<TOUT*>(ob + o) = (TOUT)value(s);
             o += st;
         }
-        if (full) out[o] = (TOUT)value(CL - 1, o);
+        if (full) *reinterpret_cast<TOUT*>(ob + o) = (TOUT)value(CL - 1);
     };
 
     if (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE) {
-        // z = Lm^T y and the back substitution of S^{-1} z, fused (highest degree first)
+        // z = Lm^T y and the back substitution of S^{-1} z, fused (highest degree first):
+        // y'_s = b1 y_s + b2 y_{s+1} + b3 y'_{s+1}
         if (act) {
             double yo_n = 0.0, yp_n = 0.0;
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
                 const int m = pi + 2 * s;
                 const double yo = y[s];
-                double z = CF(m, 2) * yo;
-                double v = 0.0;
-                if (s + 1 < CL) {
-                    z += CF(m + 2, 3) * yo_n;
-                    v = CF(m + 2, 1) * yp_n;
-                }
-                const double yp = (z - v) * CF(m, 0);
+                double yp = PT(m, 0) * yo;
+                if (s + 1 < CL) yp += PT(m, 1) * yo_n + PT(m, 2) * yp_n;
                 y[s] = yp;
                 yo_n = yo;
                 yp_n = yp;
@@ -180,14 +180,13 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
         if (act) {
             if (vhat(d.bc, n, e)) xl = A[hov(d.bc, e)];
             if (vhat(d.bc, n, e + 1)) xr = A[hov(d.bc, e + 1)];
+            // x_s = c1 y'_s + c2 x_{s-1}; the head also removes the hat coupling
             double prev = 0.0;
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
                 const int m = pi + 2 * s;
-                double v = y[s];
-                if (s == 0) v -= FS.cpl[4 * e + 2 * pi] * xl + FS.cpl[4 * e + 2 * pi + 1] * xr;
-                else v -= CF(m, 1) * prev;
-                prev = v * CF(m, 0);
+                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * PT(m, 3);
+                else prev = PT(m, 3) * y[s] + PT(m, 4) * prev;
                 y[s] = prev;
             }
             H1[c] = y[0];
@@ -195,7 +194,7 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
         if (MODE == SWEEP_SOLVE) {
             if (act) {
                 TOUT* out = reinterpret_cast<TOUT*>(a.out);
-                store_chain(out, a.lout, [&](int s, int) { return y[s]; });
+                store_chain(out, a.lout, [&](int s) { return y[s]; });
                 if (c < nh) out[IDX(a.lout, line, c)] = (TOUT)A[c];
             }
             return;
@@ -205,29 +204,26 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
         // first; a bubble entry of u is final once computed (the hat block of Lm^T does not
         // feed back into the bubbles), so g - u is stored as it is produced.
         if (act) {
-            const TIN* g = reinterpret_cast<const TIN*>(a.g);
-            TOUT* out = reinterpret_cast<TOUT*>(a.out);
-            int og, sg, oo, so;
-            chain0(a.lg, og, sg);
-            chain0(a.lout, oo, so);
+            const char* gb = reinterpret_cast<const char*>(a.g);
+            char* ob = reinterpret_cast<char*>(a.out);
+            unsigned og, sg, oo, so;
+            chain0(a.lg, og, sg, sizeof(TIN));
+            chain0(a.lout, oo, so, sizeof(TOUT));
             og += (CL - 1) * sg;
             oo += (CL - 1) * so;
-            const double tde = tau * d.delta[0];
+            const double hterm = pi == 0 ? (xl + xr) * (1.0 / 6.0) : (xr - xl) * (1.0 / 30.0);
             double x_n = 0.0, u_n = 0.0;
+            // u_s = a1 x_s + a2 x_{s-1} + a3 x_{s+1} + a4 u_{s+1} (+ the hat term at the head)
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
                 const int m = pi + 2 * s;
                 const double x = y[s];
-                double v = (kap * CF(m, 5) + tau * CF(m, 6)) * x;
-                double w = 0.0;
-                if (s > 0) v += tau * CF(m - 2, 7) * y[s - 1];
-                if (s + 1 < CL) {
-                    v += tau * CF(m, 7) * x_n;
-                    w = CF(m + 2, 3) * u_n;
-                }
-                if (s == 0) v += pi == 0 ? tde * (xl + xr) * (1.0 / 6.0) : tde * (xr - xl) * (1.0 / 30.0);
-                const double u = (v - w) * CF(m, 4);
-                if (s < CL - 1 || full) out[oo] = (TOUT)((double)g[og] - u);
+                double u = PT(m, 5) * x;
+                if (s > 0) u += PT(m, 6) * y[s - 1];
+                if (s + 1 < CL) u += PT(m, 7) * x_n + PT(m, 8) * u_n;
+                if (s == 0) u += PT(m, 12) * hterm;
+                if (s < CL - 1 || full)
+                    *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)((double)*reinterpret_cast<const TIN*>(gb + og) - u);
                 og -= sg;
                 oo -= so;
                 x_n = x;
@@ -277,18 +273,16 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
         // u = Lm^{-T} y: chain back substitution (entries final as computed, stored at once),
         // then the hat block
         if (act) {
-            TOUT* out = reinterpret_cast<TOUT*>(a.out);
-            int oo, so;
-            chain0(a.lout, oo, so);
+            char* ob = reinterpret_cast<char*>(a.out);
+            unsigned oo, so;
+            chain0(a.lout, oo, so, sizeof(TOUT));
             oo += (CL - 1) * so;
             double u_n = 0.0;
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
                 const int m = pi + 2 * s;
-                double v = y[s];
-                if (s + 1 < CL) v -= CF(m + 2, 3) * u_n;
-                u_n = v * CF(m, 4);
-                if (s < CL - 1 || full) out[oo] = (TOUT)u_n;
+                u_n = PT(m, 9) * y[s] + (s + 1 < CL ? PT(m, 11) * u_n : 0.0);
+                if (s < CL - 1 || full) *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)u_n;
                 oo -= so;
             }
             H2[c] = u_n;
@@ -319,26 +313,22 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
             if (vhat(d.bc, n, e)) xl = A[hov(d.bc, e)];
             if (vhat(d.bc, n, e + 1)) xr = A[hov(d.bc, e + 1)];
             double prev = 0.0;
+            double* out = reinterpret_cast<double*>(a.out);
+            char* ob = reinterpret_cast<char*>(a.out);
+            const double* w = d.mdiag;
+            unsigned o, st;
+            chain0(a.lout, o, st, sizeof(double));
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
                 const int m = pi + 2 * s;
-                double v = y[s];
-                if (s == 0) v -= FM.cpl[4 * e + 2 * pi] * xl + FM.cpl[4 * e + 2 * pi + 1] * xr;
-                else v -= CF(m, 3) * prev;
-                prev = v * CF(m, 4);
-                y[s] = prev;
-            }
-            double* out = reinterpret_cast<double*>(a.out);
-            const double* w = d.mdiag;
-            int o, st;
-            chain0(a.lout, o, st);
-#pragma unroll
-            for (int s = 0; s < CL; ++s) {
+                if (s == 0) prev = (y[0] - FM.cpl[4 * e + 2 * pi] * xl - FM.cpl[4 * e + 2 * pi + 1] * xr) * PT(m, 9);
+                else prev = PT(m, 9) * y[s] + PT(m, 10) * prev;
                 if (s < CL - 1 || full) {
                     const int pos = nh + 2 * s * n + c;
-                    const double u = a.accumulate ? out[o] + y[s] : y[s];
-                    out[o] = u;
-                    sdx += w[pos] * y[s] * y[s];
+                    double* po = reinterpret_cast<double*>(ob + o);
+                    const double u = a.accumulate ? *po + prev : prev;
+                    *po = u;
+                    sdx += w[pos] * prev * prev;
                     su += w[pos] * u * u;
                 }
                 o += st;
