@@ -77,7 +77,7 @@ typedef struct {
 typedef struct {
     double inner_tol;   /* mixed mode: tolerance of each FP32 ADI solve (0 = 1e-5) */
     int max_rounds;     /* mixed mode: refinement round limit (0 = 8) */
-    int lines_per_block; /* half-sweep workgroup width, 4 or 8 lines (0 = automatic) */
+    int lines_per_block; /* half-sweep workgroup width, 4 or 8 lines (0 = 8) */
     int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
     int reserved[4];
 } hpadi_options;
@@ -167,9 +167,10 @@ void hpadi_plan_destroy(hpadi_plan plan);
  * clears the totals and starts recording, 0 stops.  At most 65536 launches are
  * recorded per enable; later launches run untimed. */
 int hpadi_plan_timing(hpadi_plan plan, int enable);
-/* Totals since the last enable, by kind: 0 = column half-sweeps of the ADI
- * loop, 1 = row half-sweeps, 2 = the transforms into and out of the
- * mass-balanced coordinates.  ms[k]: summed kernel durations; bytes[k]: summed
+/* Totals since the last enable, by kind: 0 = full column half-sweeps of the
+ * ADI loop, 1 = full row half-sweeps, 2 = the others: the transforms into the
+ * mass-balanced coordinates, the last column half-sweep of each solve (a solve
+ * only) and the final mass solve back to U.  ms[k]: summed kernel durations; bytes[k]: summed
  * algorithmic HBM bytes of those launches (every array entry read or written
  * once: input, G~ and output of a fused sweep); count[k]: launches.  Any
  * pointer may be NULL.  Synchronises the stream. */

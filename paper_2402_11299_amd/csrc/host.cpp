@@ -593,7 +593,8 @@ hpadi::Layout user_layout(const hpadi_plan_s* P, long ld) {
 }
 
 // Launch a half-sweep, bracketed by timing events when measurement is enabled.
-// kind: 0 column sweep, 1 row sweep, 2 final/transform; bytes: algorithmic HBM bytes.
+// kind: 0 full column sweep, 1 full row sweep, 2 the others (transforms, the last
+// column solve, the final solve); bytes: algorithmic HBM bytes.
 int timed_sweep(hpadi_plan_s* P, bool column, const hpadi::SweepArgs& a, int mode, int tin, int tout, int kind,
                 double bytes) {
     hpadi_plan_s::Rec* r = nullptr;
@@ -684,7 +685,7 @@ int run_adi(hpadi_plan_s* P, int ts, double* U, long ldu, bool accumulate) {
         c.kappa = 1.0;
         const bool last = j + 1 == P->J;
         c.tau = last ? 0.0 : half - P->P[j + 1];
-        rc = timed_sweep(P, true, c, last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts, 0,
+        rc = timed_sweep(P, true, c, last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts, last ? 2 : 0,
                          dofs * (last ? 2.0 : 3.0) * ts);
         if (rc != HPADI_OK) return rc;
     }
@@ -951,10 +952,8 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     const int Nx = x->N, Ny = y->N;
     P->ldw = ((long)Ny + 63) / 64 * 64;
     hpadi::Layout& L = P->lint;
-    // 4-line workgroups (two per compute unit) when both axes allow the uniform fast path
-    // with 16 chains per wavefront; 8-line workgroups otherwise.
-    const int pw = P->opt.lines_per_block == 8 ? 8
-                   : (P->opt.lines_per_block == 4 || (x->n % 16 == 0 && y->n % 16 == 0)) ? 4 : 8;
+    // 8-line workgroups unless 4 are asked for (measured faster in FP32 at n = p = 64)
+    const int pw = P->opt.lines_per_block == 4 ? 4 : 8;
     L.panel = pw;
     L.nhr = x->nh;
     L.nhc = y->nh;

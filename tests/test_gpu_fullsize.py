@@ -1,0 +1,54 @@
+"""GPU parity at the full benchmark size, n = p = 64 (N = 4095 Dirichlet, 4097
+Neumann), in the launch configuration bench.py times.
+
+The exact discrete solution is known by construction (round trip): U0 is drawn,
+G0 = A_Y^x U0 M^y + M^x U0 A_Y^y is formed by the FP64 oracle, the GPU solves
+G0, and the relative L2 function error against U0 (the norm of the ADI lemma,
+Sec. 5.1) must meet the requested tolerance 1e-10.  Two draws: coefficients
+decaying like (1+k)^-2 in the degree (the shape of a solution for the
+benchmark's right-hand sides) and flat N(0,1) coefficients (every mode equally
+excited, the hardest case for the refinement).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import adi as oadi
+from oracle import basis as obasis
+from tests.gpu_helpers import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X GPU")]
+
+CASES = [(workloads.CFG_MIXED_4K_D, "mixed"), (workloads.CFG_MIXED_4K_N, "mixed"),
+         (workloads.CFG_MIXED_4K_D, "fp64"), (workloads.CFG_MIXED_4K_N, "fp64")]
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2402_11299_amd import hpadi
+    hpadi.lib()
+    return hpadi
+
+
+@pytest.mark.parametrize("cfg,prec", CASES, ids=lambda v: getattr(v, "name", v))
+@pytest.mark.parametrize("draw", ["decaying", "flat"])
+def test_full_size_round_trip(hp, cfg, prec, draw):
+    import torch
+    print(f"full-size round trip {cfg.name} {prec} {draw}", flush=True)
+    ox = obasis.assemble(obasis.make_basis(cfg.nx, cfg.px, cfg.ax, cfg.bx, cfg.bc))
+    oy = obasis.assemble(obasis.make_basis(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc))
+    if draw == "decaying":
+        U0 = workloads.decaying_coefficients(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.bc, seed=cfg.seed + 100)
+    else:
+        U0 = np.random.default_rng(cfg.seed + 200).standard_normal((ox.basis.N, oy.basis.N))
+    G0 = oadi.apply_operator(ox, oy, cfg.omega2, U0)
+    x = hp.Op1D(cfg.nx, cfg.px, cfg.ax, cfg.bx, cfg.bc)
+    y = hp.Op1D(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc)
+    plan = hp.Plan(x, y, cfg.omega2, cfg.tol, prec)
+    U, st = plan.solve(torch.from_numpy(G0).cuda())
+    err = oadi.rel_l2_error(U.cpu().numpy(), U0, ox, oy)
+    print(f"  rounds={st.rounds} J={st.J} est={st.est_rel_err:.2e} err={err:.2e}", flush=True)
+    assert st.status == hp.HPADI_OK
+    assert err <= cfg.tol
+    plan.close()

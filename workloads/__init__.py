@@ -56,6 +56,22 @@ def legendre_rhs(nx: int, px: int, ny: int, py: int, seed: int) -> np.ndarray:
     return Z * (1.0 + kx)[:, None] ** -2 * (1.0 + ky)[None, :] ** -2
 
 
+def q_degrees(n: int, p: int, bc: str) -> np.ndarray:
+    """Polynomial degree of each coefficient in the degree-major hat+bubble order:
+    hats have degree 1, the bubble block W_m (m = 0..p-2) degree m + 2."""
+    nh = n - 1 if bc == "dirichlet" else n + 1
+    return np.concatenate([np.ones(nh, dtype=np.int64), 2 + np.arange(n * (p - 1)) // n])
+
+
+def decaying_coefficients(nx: int, px: int, ny: int, py: int, bc: str, seed: int) -> np.ndarray:
+    """A random coefficient array U in the hat+bubble basis with entries
+    Z (1+kx)^-2 (1+ky)^-2, k the degree of the basis function (round-trip tests)."""
+    rng = np.random.default_rng(seed)
+    kx, ky = q_degrees(nx, px, bc), q_degrees(ny, py, bc)
+    Z = rng.standard_normal((kx.size, ky.size))
+    return Z * (1.0 + kx)[:, None] ** -2 * (1.0 + ky)[None, :] ** -2
+
+
 # The problem families (uniform meshes, both axes share the BC):
 CFG_SMALL = Problem("poisson_n4_p8_dirichlet", 4, 8, 4, 8, 0.0, "dirichlet", 1e-12, 0)
 CFG_FP64_1K = Problem("screened_n32_p32_dirichlet_w2_10", 32, 32, 32, 32, 10.0, "dirichlet",
