@@ -1,7 +1,8 @@
 """Benchmark of the ADI hp-FEM screened-Poisson solve on one MI355X.
 
 A step is one whole solve, G resident in HBM -> U resident in HBM: the
-mixed-precision solver (FP32 ADI sweeps, FP64 residual and refinement) on
+mixed-precision solver (a first ADI round with FP32 storage between the
+half-sweeps, then FP64 refinement rounds on the FP64 residual) on
 -Laplace(u) = f, zero Dirichlet, [0,1]^2, n = p = 64 (N = 4095 per dimension),
 relative error 1e-10.  Reported beside it: FP64 ADI on the same problem and GPU,
 the Neumann variant (omega^2 = 1, N = 4097), the roofline of the dominant
@@ -135,6 +136,40 @@ def cpu_baseline(cfg, interval, j_full, j_sample=1):
                        f"scaled to {j_full} iterations; BLAS threads={cores}, os.cpu_count={os.cpu_count()}")}
 
 
+def varcoef_fcg(hp, torch, steps=3):
+    """-div(a grad u) = f, n = p = 32 (N = 1023), a = 1 + exp(g)/2 with g a Gaussian random
+    field: flexible CG (one kept direction) preconditioned by the FP64 ADI solve of the
+    constant-coefficient operator at tolerance 1e-4, to a relative residual of 1e-10."""
+    import numpy as np
+    import workloads
+    cfg = workloads.CFG_VARCOEF_1K
+    x = hp.Op1D(cfg.nx, cfg.px, 0.0, 1.0, cfg.bc)
+    y = hp.Op1D(cfg.ny, cfg.py, 0.0, 1.0, cfg.bc)
+    xs, _ = hp.VarCoef.grid(x)
+    ys, _ = hp.VarCoef.grid(y)
+    a = torch.from_numpy(workloads.grf_coefficient(xs, ys, seed=cfg.seed)).cuda()
+    vc = hp.VarCoef(x, y, a)
+    pre = hp.Plan(x, y, 0.0, 1e-4, "fp64")
+    b = pre.load(torch.from_numpy(workloads.legendre_rhs(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.seed)).cuda())
+    res = {}
+    for name, m in (("pcg", 0), ("fcg1", 1)):
+        vc.solve(b, pre, tol=cfg.tol, maxit=300, truncation=m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st, _ = vc.solve(b, pre, tol=cfg.tol, maxit=300, truncation=m)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        res[name] = {"iters": st.iters, "ms": t * 1e3, "true_rel_res": st.true_rel_res,
+                     "dof_per_s": x.N * y.N / t}
+    log(f"varcoef n=p=32: pcg {res['pcg']['iters']} it {res['pcg']['ms']:.1f} ms; "
+        f"fcg1 {res['fcg1']['iters']} it {res['fcg1']['ms']:.1f} ms")
+    pre.close()
+    vc.close()
+    return {"workload": "varcoef_n32_p32_grf: -div(a grad u) = f, a = 1 + exp(g)/2, N = 1023, tol 1e-10",
+            **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,13 +213,14 @@ def main():
     hp.hpadi_plan_timing(pm.handle, False)
     N2 = x.N * y.N
     log(f"mixed: {t_mixed*1e3:.3f} ms/solve, rounds={st_mixed.rounds}, est={st_mixed.est_rel_err:.2e}")
-    kinds = ["column_sweep_full", "row_sweep_full", "transform_solve_final"]
+    kinds = ["column_sweep_full_fp32", "row_sweep_full_fp32", "transform_solve_final_fp32",
+             "column_sweep_full_fp64", "row_sweep_full_fp64", "transform_solve_final_fp64"]
     per_kernel = {}
-    for k in range(3):
+    for k in range(6):
         if ct[k]:
             per_kernel[kinds[k]] = {"launches": ct[k], "avg_us": ms[k] / ct[k] * 1e3,
                                     "GBps": by[k] / (ms[k] * 1e-3) / 1e9}
-    # the dominant kernel: the full column half-sweep (FP32 in/out, FP64 registers)
+    # the dominant kernel: the full FP32-storage column half-sweep (FP64 registers)
     dom = 0
     launches_per_step = ct[dom] / (args.steps + args.warmup)
     cl = cfgD.px // 2
@@ -235,6 +271,9 @@ def main():
         pmn.close()
         pfn.close()
 
+    if not args.only_mixed:
+        out["varcoef_fcg"] = varcoef_fcg(hp, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         j_full = hp.hpadi_shifts(pm.interval, cfgD.tol)[0]
@@ -252,12 +291,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 sweeps + f64 residual/refinement",
+        "dtype": "f32 first-round sweeps + f64 residual and refinement rounds",
         "data": "synthetic",
         "config": {"workload": "poisson_n64_p64_dirichlet: -Laplace u = f on [0,1]^2, zero Dirichlet, "
                                "n=p=64 (N=4095 per dim), random Legendre f (seed 2), mixed precision, rel err 1e-10",
                    "N": x.N, "n": cfgD.nx, "p": cfgD.px, "tol": cfgD.tol, "J_inner": pm.J,
-                   "rounds": st_mixed.rounds, "est_rel_err": st_mixed.est_rel_err,
+                   "rounds": st_mixed.rounds, "fp32_rounds": st_mixed.fp32_rounds,
+                   "est_rel_err": st_mixed.est_rel_err,
                    "rel_err_vs_oracle_roundtrip": err_rt, "plan_ms": t_plan_mixed * 1e3},
         "roofline": roof,
         "kernels": per_kernel,

@@ -70,16 +70,19 @@ typedef struct {
     double interval[4];  /* [a, b, c, d] used by the plan */
     double est_rel_err;  /* estimated relative error of U (mixed mode) */
     double res_rel;      /* last FP64 relative residual ||G - A U|| / ||G|| (mixed mode) */
-    double t_ms[4];      /* reserved */
+    int fp32_rounds;     /* rounds run with FP32 sweeps (mixed mode) */
+    int reserved0;
+    double t_ms[3];      /* reserved */
 } hpadi_stats;
 
 /* Options for hpadi_plan_create_ex (zero-initialise, then set fields). */
 typedef struct {
-    double inner_tol;   /* mixed mode: tolerance of each FP32 ADI solve (0 = 1e-5) */
+    double inner_tol;   /* mixed mode: tolerance of the shift family of every round (0 = 3e-6) */
     int max_rounds;     /* mixed mode: refinement round limit (0 = 8) */
     int lines_per_block; /* half-sweep workgroup width, 4 or 8 lines (0 = 8) */
     int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
-    int reserved[4];
+    int fp32_rounds;    /* mixed mode: leading rounds with FP32 sweeps; later rounds are FP64 (0 = 1) */
+    int reserved[3];
 } hpadi_options;
 
 /* ---- 1D operators (Sec. 2, Sec. 3.1, App. A) -------------------------- */
@@ -148,10 +151,13 @@ int hpadi_load(hpadi_plan plan, const double* F_dev, int ldf, double* G_dev, int
 /* Solve A_Y^x U M^y + M^x U A_Y^y = G (Alg. 2).  G_dev and U_dev are FP64
  * N_x x N_y device arrays.  FP64: J ADI iterations in FP64 (relative error
  * <= tol in the norm of the ADI lemma, Sec. 5.1).  MIXED: iterative
- * refinement with an FP64 residual and FP32 ADI sweeps until the estimated
- * relative error is <= tol.  stats may be NULL.  ENOCONV if the round limit
- * is reached (U holds the last iterate).  Synchronises the stream in MIXED
- * mode (one scalar read-back per round). */
+ * refinement on the FP64 residual, every round an ADI solve with the plan's
+ * shift family (tolerance inner_tol): the first fp32_rounds rounds with FP32
+ * storage between half-sweeps, the later ones in FP64; the solve stops after
+ * an FP64 round once the lemma bound eps/(1-eps) ||delta|| / ||U|| (twice, for
+ * the diagonal-mass norm used) is <= tol.  stats may be NULL.  ENOCONV if the
+ * round limit is reached (U holds the last iterate).  Synchronises the stream
+ * in MIXED mode (one scalar read-back per FP64 round). */
 int hpadi_solve(hpadi_plan plan, const double* G_dev, int ldg, double* U_dev, int ldu,
                 hpadi_stats* stats);
 
@@ -159,6 +165,54 @@ int hpadi_solve(hpadi_plan plan, const double* G_dev, int ldg, double* U_dev, in
 int hpadi_apply(hpadi_plan plan, const double* U_dev, int ldu, double* Y_dev, int ldy);
 
 void hpadi_plan_destroy(hpadi_plan plan);
+
+/* ---- Variable coefficient and ADI-preconditioned CG (Sec. 7) ----------- */
+
+/* -div(a grad u) = f with the same bases and boundary conditions as the plans:
+ * the Galerkin form sum_e sum_(i,j) w_i w_j a(x_i, y_j) grad u . grad v is
+ * evaluated with q = p + 2 Gauss-Legendre points per element and dimension
+ * (exact for a polynomial a of degree <= 3 per variable).  Sec. 7 solves such
+ * a problem by CG preconditioned with the constant-coefficient ADI solve at a
+ * loose tolerance. */
+typedef struct hpadi_varcoef_s* hpadi_varcoef;
+
+/* Quadrature grid of one axis, host: x[e q + i] physical Gauss point i of
+ * element e, w[e q + i] its weight including the Jacobian delta_e / 2, q = p + 2.
+ * len >= n q.  Either pointer may be NULL. */
+int hpadi_varcoef_grid(hpadi_op1d op, double* x, double* w, int len);
+/* Operator for the coefficient a_dev[(e_x q_x + i) * lda + e_y q_y + j] =
+ * a(x_i of e_x, y_j of e_y): FP64 device memory, (n_x q_x) x (n_y q_y), copied
+ * (the caller may free it afterwards).  EINVAL when (p_x+1)(p_y+1) + (p_x+2)(p_y+1)
+ * + (p_x+2)(p_y+2) + (p_y+1)(p_y+2) doubles exceed 160 KiB (p up to about 80). */
+int hpadi_varcoef_create(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int lda, void* hip_stream,
+                         hpadi_varcoef* out);
+/* Y = A_a U (FP64 device arrays N_x x N_y, row-major), stream-ordered. */
+int hpadi_varcoef_apply(hpadi_varcoef vc, const double* U_dev, int ldu, double* Y_dev, int ldy);
+void hpadi_varcoef_destroy(hpadi_varcoef vc);
+
+typedef struct {
+    int iters;            /* Krylov iterations (operator applications) */
+    int status;           /* HPADI_OK, HPADI_ENOCONV or HPADI_ENOTSPD */
+    int precond_calls;    /* preconditioner applications */
+    int reserved0;
+    double rel_res;       /* ||r_k|| / ||b|| of the recurrence residual at exit */
+    double true_rel_res;  /* ||b - A_a x|| / ||b||, recomputed in FP64 at exit */
+    double t_ms;          /* host wall time of the call */
+    double reserved[3];
+} hpadi_krylov_stats;
+
+/* Solve A_a x = b from x = 0 until ||r_k||_2 / ||b||_2 <= tol (FP64 vectors).
+ * truncation = 0: preconditioned CG; 1..4: flexible CG keeping that many
+ * previous directions (each new direction is the preconditioned residual made
+ * A_a-orthogonal to them; alpha = d.r / d.A d).  precond: an ADI plan whose
+ * solve is the preconditioner (its N_x, N_y must match; typically omega2 = 0,
+ * tol 1e-4), or NULL for none.  res_hist (host, may be NULL) receives the
+ * relative recurrence residual of iterates 0..min(iters, hist_len-1).
+ * Synchronises the stream once per dot product.  ENOCONV after maxit
+ * iterations (x holds the last iterate); ENOTSPD if d.A d <= 0. */
+int hpadi_fcg_solve(hpadi_varcoef vc, hpadi_plan precond, const double* b_dev, int ldb, double* x_dev, int ldx,
+                    double tol, int maxit, int truncation, double* res_hist, int hist_len,
+                    hpadi_krylov_stats* stats);
 
 /* ---- Measurement ------------------------------------------------------- */
 
@@ -170,11 +224,13 @@ int hpadi_plan_timing(hpadi_plan plan, int enable);
 /* Totals since the last enable, by kind: 0 = full column half-sweeps of the
  * ADI loop, 1 = full row half-sweeps, 2 = the others: the transforms into the
  * mass-balanced coordinates, the last column half-sweep of each solve (a solve
- * only) and the final mass solve back to U.  ms[k]: summed kernel durations; bytes[k]: summed
- * algorithmic HBM bytes of those launches (every array entry read or written
- * once: input, G~ and output of a fused sweep); count[k]: launches.  Any
- * pointer may be NULL.  Synchronises the stream. */
-int hpadi_plan_timing_read(hpadi_plan plan, double ms[3], double bytes[3], int count[3]);
+ * only) and the final mass solve back to U; kinds 3, 4, 5 are the same for
+ * sweeps whose iterate storage is FP64 (FP64 plans and the FP64 rounds of mixed
+ * plans), kinds 0-2 then hold the FP32-storage sweeps.  ms[k]: summed kernel
+ * durations; bytes[k]: summed algorithmic HBM bytes of those launches (every
+ * array entry read or written once: input, G~ and output of a fused sweep);
+ * count[k]: launches.  Any pointer may be NULL.  Synchronises the stream. */
+int hpadi_plan_timing_read(hpadi_plan plan, double ms[6], double bytes[6], int count[6]);
 
 const char* hpadi_strerror(int status);
 

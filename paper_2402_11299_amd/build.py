@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhpadi.so")
 
-SOURCES = ["host.cpp", "kernels.hip", "sweep.hip", "sweep_uni.hip"]
+SOURCES = ["host.cpp", "krylov.cpp", "kernels.hip", "sweep.hip", "sweep_uni.hip", "varcoef.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -40,17 +40,36 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def _compile(src: str, obj: str, verbose: bool) -> None:
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    cmd = [hipcc(), *flags, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libhpadi.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed on {src}")
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source to an object in parallel, then link libhpadi.so."""
+    import concurrent.futures
+    import tempfile
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory(prefix="hpadi_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            for f in [ex.submit(_compile, src, obj, verbose) for src, obj in zip(SOURCES, objs)]:
+                f.result()
+        tmp = LIB + ".tmp"
+        cmd = [hipcc(), *HIPCC_FLAGS, *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libhpadi.so")
+        os.replace(tmp, LIB)
     return LIB
 
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "host_internal.h"
 
 using hpadi::DimDev;
 using hpadi::FactorLayout;
@@ -19,15 +20,6 @@ using hpadi::FactorLayout;
 // ===========================================================================
 // 1D operators (Sec. 2.2-2.3, App. A).
 // ===========================================================================
-struct hpadi_op1d_s {
-    int n, p, bc, nh, N, Nleg;
-    std::vector<double> x, delta;
-
-    bool vertex_is_hat(int v) const { return bc == HPADI_DIRICHLET ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n); }
-    int hat_of_vertex(int v) const { return bc == HPADI_DIRICHLET ? v - 1 : v; }
-    int vertex_of_hat(int h) const { return bc == HPADI_DIRICHLET ? h + 1 : h; }
-    int bubble(int m, int e) const { return nh + m * n + e; }
-};
 
 namespace {
 
@@ -423,64 +415,10 @@ int interval_of(const hpadi_op1d_s& o, double omega2, double out[2]) {
 // ===========================================================================
 // Plan.
 // ===========================================================================
-struct DimHost {
-    hpadi_op1d_s op;
-    DimDev dev{};
-    double* buf = nullptr;  // device: delta, invdelta, mdiag, tab64
-    float* tab32 = nullptr;
-    int hpad = 0;           // hats padded to a multiple of 8 (internal layout)
-    int Npad = 0;           // internal length: hpad + (p-1) n
-    bool uniform = false;   // all elements of equal width and n % 8 == 0 (per-degree coefficient fast path)
-};
-
-struct hpadi_plan_s {
-    DimHost dx, dy;
-    double omega2 = 0.0, tol = 0.0;
-    int precision = HPADI_FP64;
-    hpadi_options opt{};
-    double interval[4] = {0, 0, 0, 0};
-    int J = 0;
-    std::vector<double> P, Q;
-    hipStream_t stream = nullptr;
-    bool shared = false;          // x and y use one factor family
-    FactorLayout flx{}, fly{};
-    double* facx64 = nullptr;     // J+1 records: K_x + (w/2 - q_j) M_x, then M_x
-    double* facy64 = nullptr;     // J+1 records: K_y + (w/2 + p_j) M_y, then M_y
-    double* coefx = nullptr;      // uniform meshes: (J+1) (p_x-1) 8 per-degree coefficient records
-    double* coefy = nullptr;
-    double* ptabx = nullptr;      // uniform meshes: J folded per-pass tables (p_x records of 16 doubles)
-    double* ptaby = nullptr;
-    int* status = nullptr;
-    // work arrays in the internal panel layout
-    hpadi::Layout lint{};
-    size_t nint = 0;              // elements per internal array
-    void* Wk = nullptr;           // balanced iterate (TS)
-    void* Gt = nullptr;           // balanced right-hand side G~ (TS)
-    double* T64 = nullptr;        // transform temporary (FP64, internal layout)
-    // FP64 row-major work (mixed refinement, apply)
-    long ldw = 0;
-    double* T1 = nullptr;
-    double* T2 = nullptr;
-    double* R64 = nullptr;
-    double* H = nullptr;          // load temporary (Nleg_x x N_y)
-    long ldh = 0;
-    double* acc = nullptr;        // device accumulators
-    double* acc_host = nullptr;   // pinned host copy
-    // measurement
-    bool timing = false;
-    struct Rec { hipEvent_t a, b; int kind; double bytes; };
-    std::vector<Rec> recs;        // event pool; the first nrec are in use
-    size_t nrec = 0;
-};
 
 namespace {
 
-template <typename T>
-hipError_t dmalloc(T** p, size_t count) {
-    *p = nullptr;
-    if (count == 0) return hipSuccess;
-    return hipMalloc((void**)p, count * sizeof(T));
-}
+using hpadi_host::dmalloc;
 
 int make_dim(DimHost& D, const hpadi_op1d_s& o) {
     D.op = o;
@@ -594,7 +532,8 @@ hpadi::Layout user_layout(const hpadi_plan_s* P, long ld) {
 
 // Launch a half-sweep, bracketed by timing events when measurement is enabled.
 // kind: 0 full column sweep, 1 full row sweep, 2 the others (transforms, the last
-// column solve, the final solve); bytes: algorithmic HBM bytes.
+// column solve, the final solve), plus 3 when the sweep stores FP64; bytes:
+// algorithmic HBM bytes.
 int timed_sweep(hpadi_plan_s* P, bool column, const hpadi::SweepArgs& a, int mode, int tin, int tout, int kind,
                 double bytes) {
     hpadi_plan_s::Rec* r = nullptr;
@@ -605,7 +544,8 @@ int timed_sweep(hpadi_plan_s* P, bool column, const hpadi::SweepArgs& a, int mod
             P->recs.push_back(nr);
         }
         r = &P->recs[P->nrec++];
-        r->kind = kind;
+        // FP64 storage (either side of the sweep 8-byte) goes to kinds 3..5
+        r->kind = kind + ((tin == 8 && tout == 8) || (mode != hpadi::SWEEP_TRANSFORM && mode != hpadi::SWEEP_FINAL && tin == 8) ? 3 : 0);
         r->bytes = bytes;
         if (hipEventRecord(r->a, P->stream) != hipSuccess) return HPADI_EHIP;
     }
@@ -857,7 +797,8 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     hpadi_plan_s* P = new (std::nothrow) hpadi_plan_s;
     if (!P) return HPADI_ENOMEM;
     if (opts) P->opt = *opts;
-    if (!(P->opt.inner_tol > 0.0)) P->opt.inner_tol = 1e-5;
+    if (!(P->opt.inner_tol > 0.0)) P->opt.inner_tol = 3e-6;
+    if (P->opt.fp32_rounds <= 0) P->opt.fp32_rounds = 1;
     if (P->opt.max_rounds <= 0) P->opt.max_rounds = 8;
     P->omega2 = omega2;
     P->tol = tol;
@@ -878,6 +819,7 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
         P->interval[3] = -iy[0];
     }
     const double adi_tol = precision == HPADI_FP64 ? tol : std::max(P->opt.inner_tol, tol);
+    P->adi_eps = adi_tol;
     if ((rc = compute_shifts(P->interval, adi_tol, 0, &P->J, P->P, P->Q)) != HPADI_OK) { plan_free(P); return rc; }
     if ((rc = make_dim(P->dx, *x)) != HPADI_OK || (rc = make_dim(P->dy, *y)) != HPADI_OK) { plan_free(P); return rc; }
     const int J = P->J;
@@ -962,8 +904,8 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     L.ld = (long)P->dx.Npad * pw;
     const long panels = (P->dy.Npad + pw - 1) / pw;
     P->nint = (size_t)panels * L.ld;
-    const size_t ts = precision == HPADI_FP64 ? 8 : 4;
-    bool ok = hipMalloc(&P->Wk, P->nint * ts) == hipSuccess && hipMalloc(&P->Gt, P->nint * ts) == hipSuccess &&
+    // 8-byte elements in both modes: mixed plans run FP64 refinement rounds as well
+    bool ok = hipMalloc(&P->Wk, P->nint * 8) == hipSuccess && hipMalloc(&P->Gt, P->nint * 8) == hipSuccess &&
               dmalloc(&P->T64, P->nint) == hipSuccess;
     ok = ok && dmalloc(&P->acc, 8) == hipSuccess && hipHostMalloc((void**)&P->acc_host, 8 * sizeof(double)) == hipSuccess;
     if (!ok) { plan_free(P); return HPADI_ENOMEM; }
@@ -1050,20 +992,33 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
         st.iters = P->J;
         st.est_rel_err = P->tol;
     } else {
-        // Iterative refinement: U = 0; repeat { delta = ADI_fp32(r); U += delta; r = G - A U (FP64) }.
+        // Iterative refinement: U = 0; repeat { delta = ADI(r); U += delta; r = G - A U (FP64) }.
+        // The first fp32_rounds rounds run the ADI sweeps in FP32 storage; the later ones in
+        // FP64, where the ADI lemma bounds the error of the round: with e the error before
+        // the round and delta its correction, ||e - delta|| <= eps ||e|| and ||e|| <= ||delta||
+        // / (1 - eps), so ||U* - U|| <= eps / (1 - eps) ||delta|| (eps: tolerance of the
+        // shift family).  Norms are diagonal-mass weighted; kNormSafety covers the ratio of
+        // that norm to the L2 norm.  FP32 rounds have no such bound (their rounding floor
+        // depends on the spectrum of the residual) and never end the solve.
         if ((rc = ensure_fp64_work(P)) != HPADI_OK) return rc;
         if (!P->R64 && dmalloc(&P->R64, (size_t)Nx * P->ldw) != hipSuccess) return HPADI_ENOMEM;
         if (hpadi::launch_zero_f64(U, ldu, Nx, Ny, s) != hipSuccess) return HPADI_EHIP;
-        double nd_prev = 0.0, est = 1.0;
+        constexpr double kNormSafety = 2.0;
+        const double eps = P->adi_eps;
+        double est = 1.0;
         const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
         int k = 0;
         bool done = false;
         for (k = 1; k <= maxr; ++k) {
+            const bool fp32 = k <= P->opt.fp32_rounds;
+            const int ts = fp32 ? 4 : 8;
             if (hipMemsetAsync(P->acc, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
-            if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, 4)) != HPADI_OK) return rc;
-            if ((rc = run_adi(P, 4, U, ldu, true)) != HPADI_OK) return rc;
+            if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
+            if ((rc = run_adi(P, ts, U, ldu, true)) != HPADI_OK) return rc;
             st.iters += P->J;
-            if (P->opt.fixed_rounds <= 0) {
+            if (fp32) st.fp32_rounds++;
+            const bool decide = P->opt.fixed_rounds <= 0 && !fp32;
+            if (decide || k == maxr) {
                 if (hipMemcpyAsync(P->acc_host, P->acc, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)
                     return HPADI_EHIP;
@@ -1073,18 +1028,13 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
                     const double gnorm = std::sqrt(std::max(P->acc_host[3], 0.0));
                     st.res_rel = gnorm > 0 ? std::sqrt(std::max(P->acc_host[2], 0.0)) / gnorm : 0.0;
                 }
-                // error after this round ~ rho ||delta_k||, rho the observed contraction per round
-                const double rho = (k == 1) ? std::max(P->opt.inner_tol, 1e-6)
-                                            : std::min(1.0, nd / std::max(nd_prev, 1e-300));
-                est = nu > 0 ? rho * nd / nu : 0.0;
-                nd_prev = nd;
+                est = fp32 ? 1.0 : (nu > 0 ? kNormSafety * eps / (1.0 - eps) * nd / nu : 0.0);
                 if (!std::isfinite(est)) break;
-                if (est <= P->tol) {
+                if (decide && est <= P->tol) {
                     done = true;
                     break;
                 }
-            } else if (k == maxr) {
-                break;
+                if (k == maxr) break;
             }
             // r = G - A U in FP64
             if ((rc = row_products(P, U, ldu)) != HPADI_OK) return rc;
@@ -1123,11 +1073,11 @@ int hpadi_plan_timing(hpadi_plan P, int enable) {
     return HPADI_OK;
 }
 
-int hpadi_plan_timing_read(hpadi_plan P, double ms[3], double bytes[3], int count[3]) {
+int hpadi_plan_timing_read(hpadi_plan P, double ms[6], double bytes[6], int count[6]) {
     if (!P) return HPADI_EINVAL;
     if (hipStreamSynchronize(P->stream) != hipSuccess) return HPADI_EHIP;
-    double t[3] = {0, 0, 0}, b[3] = {0, 0, 0};
-    int c[3] = {0, 0, 0};
+    double t[6] = {0, 0, 0, 0, 0, 0}, b[6] = {0, 0, 0, 0, 0, 0};
+    int c[6] = {0, 0, 0, 0, 0, 0};
     for (size_t i = 0; i < P->nrec; ++i) {
         float e = 0.0f;
         if (hipEventElapsedTime(&e, P->recs[i].a, P->recs[i].b) != hipSuccess) return HPADI_EHIP;
@@ -1136,7 +1086,7 @@ int hpadi_plan_timing_read(hpadi_plan P, double ms[3], double bytes[3], int coun
         b[k] += P->recs[i].bytes;
         c[k] += 1;
     }
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 6; ++k) {
         if (ms) ms[k] = t[k];
         if (bytes) bytes[k] = b[k];
         if (count) count[k] = c[k];

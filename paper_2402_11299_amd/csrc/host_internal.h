@@ -1,0 +1,83 @@
+// Host-side state shared by the host sources of hpadi: 1D operators and plans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "hpadi.h"
+#include "internal.h"
+
+// 1D operator (Sec. 2.2-2.3, App. A): mesh, degree and boundary condition.
+struct hpadi_op1d_s {
+    int n, p, bc, nh, N, Nleg;
+    std::vector<double> x, delta;
+
+    bool vertex_is_hat(int v) const { return bc == HPADI_DIRICHLET ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n); }
+    int hat_of_vertex(int v) const { return bc == HPADI_DIRICHLET ? v - 1 : v; }
+    int vertex_of_hat(int h) const { return bc == HPADI_DIRICHLET ? h + 1 : h; }
+    int bubble(int m, int e) const { return nh + m * n + e; }
+};
+
+// One axis of a plan: the operator and its device-side description.
+struct DimHost {
+    hpadi_op1d_s op;
+    hpadi::DimDev dev{};
+    double* buf = nullptr;  // device: delta, invdelta, mdiag, tab64
+    float* tab32 = nullptr;
+    int hpad = 0;           // hats padded to a multiple of 8 (internal layout)
+    int Npad = 0;           // internal length: hpad + (p-1) n
+    bool uniform = false;   // all elements of equal width and n % 8 == 0 (per-degree coefficient fast path)
+};
+
+struct hpadi_plan_s {
+    DimHost dx, dy;
+    double omega2 = 0.0, tol = 0.0;
+    int precision = HPADI_FP64;
+    hpadi_options opt{};
+    double interval[4] = {0, 0, 0, 0};
+    int J = 0;
+    double adi_eps = 0.0;         // tolerance the shift family was built for
+    std::vector<double> P, Q;
+    hipStream_t stream = nullptr;
+    bool shared = false;          // x and y use one factor family
+    hpadi::FactorLayout flx{}, fly{};
+    double* facx64 = nullptr;     // J+1 records: K_x + (w/2 - q_j) M_x, then M_x
+    double* facy64 = nullptr;     // J+1 records: K_y + (w/2 + p_j) M_y, then M_y
+    double* coefx = nullptr;      // uniform meshes: (J+1) (p_x-1) 8 per-degree coefficient records
+    double* coefy = nullptr;
+    double* ptabx = nullptr;      // uniform meshes: J folded per-pass tables (p_x records of 16 doubles)
+    double* ptaby = nullptr;
+    int* status = nullptr;
+    // work arrays in the internal panel layout
+    hpadi::Layout lint{};
+    size_t nint = 0;              // elements per internal array
+    void* Wk = nullptr;           // balanced iterate (TS)
+    void* Gt = nullptr;           // balanced right-hand side G~ (TS)
+    double* T64 = nullptr;        // transform temporary (FP64, internal layout)
+    // FP64 row-major work (mixed refinement, apply)
+    long ldw = 0;
+    double* T1 = nullptr;
+    double* T2 = nullptr;
+    double* R64 = nullptr;
+    double* H = nullptr;          // load temporary (Nleg_x x N_y)
+    long ldh = 0;
+    double* acc = nullptr;        // device accumulators
+    double* acc_host = nullptr;   // pinned host copy
+    // measurement
+    bool timing = false;
+    struct Rec { hipEvent_t a, b; int kind; double bytes; };
+    std::vector<Rec> recs;        // event pool; the first nrec are in use
+    size_t nrec = 0;
+};
+
+namespace hpadi_host {
+
+template <typename T>
+hipError_t dmalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)p, count * sizeof(T));
+}
+
+}  // namespace hpadi_host

@@ -1,0 +1,404 @@
+// Host side of the variable-coefficient operator and of the ADI-preconditioned
+// Krylov solvers (Sec. 7: CG preconditioned by the constant-coefficient ADI
+// solve at a loose tolerance).  Declared in include/hpadi.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "host_internal.h"
+#include "hpadi.h"
+#include "krylov.h"
+
+using hpadi_host::dmalloc;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_q from the
+// Chebyshev-like initial guesses cos(pi (i - 1/4) / (q + 1/2)) (Golub-Welsch's
+// eigenvalue route gives the same rule); weights 2 / ((1 - t^2) P_q'(t)^2).
+void gauss_legendre(int q, std::vector<double>& t, std::vector<double>& w) {
+    t.assign(q, 0.0);
+    w.assign(q, 0.0);
+    for (int i = 0; i < (q + 1) / 2; ++i) {
+        double x = std::cos(kPi * (i + 0.75) / (q + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= q; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double pq = q == 0 ? 1.0 : (q == 1 ? x : p1);
+            const double pqm1 = q == 1 ? 1.0 : p0;
+            dp = q * (x * pq - pqm1) / (x * x - 1.0);
+            const double dx = pq / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) {
+                // one more evaluation of the derivative at the converged node
+                p0 = 1.0;
+                p1 = x;
+                for (int k = 2; k <= q; ++k) {
+                    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = q * (x * (q == 1 ? x : p1) - (q == 1 ? 1.0 : p0)) / (x * x - 1.0);
+                break;
+            }
+        }
+        // nodes ascending: t[i] = -x (x descending from near 1), mirrored at q-1-i
+        t[i] = -x;
+        t[q - 1 - i] = x;
+        const double wi = 2.0 / ((1.0 - x * x) * dp * dp);
+        w[i] = wi;
+        w[q - 1 - i] = wi;
+    }
+}
+
+// Values and reference derivatives at t of the local functions
+// [left hat, right hat, W_0 .. W_{p-2}], W_k = (P_k - P_{k+2}) / (2k + 3), W_k' = -P_{k+1}.
+void local_tables(int p, const std::vector<double>& t, std::vector<double>& V, std::vector<double>& D) {
+    const int q = (int)t.size(), L = p + 1;
+    V.assign((size_t)q * L, 0.0);
+    D.assign((size_t)q * L, 0.0);
+    std::vector<double> P(p + 2);
+    for (int i = 0; i < q; ++i) {
+        const double x = t[i];
+        P[0] = 1.0;
+        if (p + 1 >= 1) P[1] = x;
+        for (int k = 2; k <= p + 1; ++k) P[k] = ((2.0 * k - 1.0) * x * P[k - 1] - (k - 1.0) * P[k - 2]) / k;
+        V[i * L + 0] = (1.0 - x) / 2.0;
+        V[i * L + 1] = (1.0 + x) / 2.0;
+        D[i * L + 0] = -0.5;
+        D[i * L + 1] = 0.5;
+        for (int k = 0; k + 2 <= p; ++k) {
+            V[i * L + 2 + k] = (P[k] - P[k + 2]) / (2.0 * k + 3.0);
+            D[i * L + 2 + k] = -P[k + 1];
+        }
+    }
+}
+
+struct VcAxis {
+    int n, p, q, N;
+    std::vector<int> l2g, own;
+    std::vector<double> delta, t, w, V, D;
+};
+
+void make_axis(const hpadi_op1d_s& o, VcAxis& A) {
+    A.n = o.n;
+    A.p = o.p;
+    A.q = o.p + 2;
+    A.N = o.N;
+    A.delta = o.delta;
+    gauss_legendre(A.q, A.t, A.w);
+    local_tables(o.p, A.t, A.V, A.D);
+    const int L = o.p + 1;
+    A.l2g.assign((size_t)o.n * L, -1);
+    A.own.assign((size_t)4 * o.N, -1);
+    auto add_owner = [&](int g, int e, int l) {
+        int* ow = &A.own[4 * (size_t)g];
+        const int slot = ow[0] < 0 ? 0 : 1;
+        ow[2 * slot] = e;
+        ow[2 * slot + 1] = l;
+    };
+    for (int e = 0; e < o.n; ++e) {
+        if (o.vertex_is_hat(e)) A.l2g[e * L + 0] = o.hat_of_vertex(e);
+        if (o.vertex_is_hat(e + 1)) A.l2g[e * L + 1] = o.hat_of_vertex(e + 1);
+        for (int m = 0; m + 2 <= o.p; ++m) A.l2g[e * L + 2 + m] = o.bubble(m, e);
+        for (int l = 0; l < L; ++l)
+            if (A.l2g[e * L + l] >= 0) add_owner(A.l2g[e * L + l], e, l);
+    }
+}
+
+}  // namespace
+
+struct hpadi_varcoef_s {
+    hpadi::VarCoefDev dev{};
+    hipStream_t stream = nullptr;
+    int Nx = 0, Ny = 0;
+    std::vector<void*> allocs;
+    // Krylov work (allocated on first use): r, z, x-copy, (d, q) x (m + 1), partials, dots
+    int mwork = -1;
+    double* r = nullptr;
+    double* z = nullptr;
+    std::vector<double*> d, q;
+    double* part = nullptr;
+    double* dots = nullptr;
+    double* dots_host = nullptr;
+    ~hpadi_varcoef_s() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* p : allocs) (void)hipFree(p);
+        for (double* p : d) (void)hipFree(p);
+        for (double* p : q) (void)hipFree(p);
+        (void)hipFree(r);
+        (void)hipFree(z);
+        (void)hipFree(part);
+        (void)hipFree(dots);
+        if (dots_host) (void)hipHostFree(dots_host);
+    }
+};
+
+namespace {
+
+template <typename T>
+int upload(hpadi_varcoef_s* V, const std::vector<T>& h, const T** out) {
+    T* p = nullptr;
+    if (dmalloc(&p, h.size()) != hipSuccess) return HPADI_ENOMEM;
+    V->allocs.push_back(p);
+    if (!h.empty() && hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return HPADI_EHIP;
+    *out = p;
+    return HPADI_OK;
+}
+
+int ensure_work(hpadi_varcoef_s* V, int m) {
+    const size_t n = (size_t)V->Nx * V->Ny;
+    if (!V->r) {
+        if (dmalloc(&V->r, n) != hipSuccess || dmalloc(&V->z, n) != hipSuccess ||
+            dmalloc(&V->part, 4 * (size_t)hpadi::dot_parts()) != hipSuccess || dmalloc(&V->dots, 8) != hipSuccess)
+            return HPADI_ENOMEM;
+        if (hipHostMalloc((void**)&V->dots_host, 8 * sizeof(double)) != hipSuccess) return HPADI_ENOMEM;
+    }
+    const int need = std::max(m, 1) + 1;
+    while ((int)V->d.size() < need) {
+        double *dd = nullptr, *qq = nullptr;
+        if (dmalloc(&dd, n) != hipSuccess || dmalloc(&qq, n) != hipSuccess) {
+            (void)hipFree(dd);
+            return HPADI_ENOMEM;
+        }
+        V->d.push_back(dd);
+        V->q.push_back(qq);
+    }
+    return HPADI_OK;
+}
+
+// out[k] = a . b_k on the device, copied to V->dots_host (synchronises the stream)
+int dots(hpadi_varcoef_s* V, const double* a, std::initializer_list<const double*> bs, double* res) {
+    hpadi::MultiB mb{};
+    mb.nb = 0;
+    for (const double* b : bs) mb.b[mb.nb++] = b;
+    const long n = (long)V->Nx * V->Ny;
+    if (hpadi::launch_multidot(a, mb, n, V->part, V->dots, V->stream) != hipSuccess) return HPADI_EHIP;
+    if (hipMemcpyAsync(V->dots_host, V->dots, mb.nb * sizeof(double), hipMemcpyDeviceToHost, V->stream) != hipSuccess ||
+        hipStreamSynchronize(V->stream) != hipSuccess)
+        return HPADI_EHIP;
+    for (int k = 0; k < mb.nb; ++k) res[k] = V->dots_host[k];
+    return HPADI_OK;
+}
+
+int axpy(hpadi_varcoef_s* V, double* y, double c, const double* x) {
+    hpadi::MultiB mb{};
+    mb.nb = 1;
+    mb.b[0] = x;
+    hpadi::Coefs cc{};
+    cc.c[0] = c;
+    return hpadi::launch_axpys(y, mb, cc, (long)V->Nx * V->Ny, V->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpadi_varcoef_grid(hpadi_op1d op, double* x, double* w, int len) {
+    if (!op) return HPADI_EINVAL;
+    const int q = op->p + 2;
+    if (len < op->n * q) return HPADI_EINVAL;
+    std::vector<double> t, wt;
+    gauss_legendre(q, t, wt);
+    for (int e = 0; e < op->n; ++e)
+        for (int i = 0; i < q; ++i) {
+            const double d = op->delta[e];
+            if (x) x[e * q + i] = op->x[e] + (t[i] + 1.0) * d / 2.0;
+            if (w) w[e * q + i] = wt[i] * d / 2.0;
+        }
+    return HPADI_OK;
+}
+
+int hpadi_varcoef_create(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int lda, void* hip_stream,
+                         hpadi_varcoef* out) {
+    if (!x || !y || !a_dev || !out) return HPADI_EINVAL;
+    *out = nullptr;
+    const int qx = x->p + 2, qy = y->p + 2;
+    if (lda < y->n * qy) return HPADI_EINVAL;
+    if (hpadi::vc_lds_bytes(x->p, y->p) > 160 * 1024) return HPADI_EINVAL;
+    hpadi_varcoef_s* V = new (std::nothrow) hpadi_varcoef_s();
+    if (!V) return HPADI_ENOMEM;
+    V->stream = (hipStream_t)hip_stream;
+    V->Nx = x->N;
+    V->Ny = y->N;
+    VcAxis ax, ay;
+    make_axis(*x, ax);
+    make_axis(*y, ay);
+    hpadi::VarCoefDev& d = V->dev;
+    d.nx = x->n; d.px = x->p; d.qx = qx; d.Nx = x->N;
+    d.ny = y->n; d.py = y->p; d.qy = qy; d.Ny = y->N;
+    int rc = HPADI_OK;
+    if ((rc = upload(V, ax.l2g, &d.l2gx)) || (rc = upload(V, ay.l2g, &d.l2gy)) || (rc = upload(V, ax.own, &d.ownx)) ||
+        (rc = upload(V, ay.own, &d.owny)) || (rc = upload(V, ax.delta, &d.delx)) || (rc = upload(V, ay.delta, &d.dely)) ||
+        (rc = upload(V, ax.w, &d.wx)) || (rc = upload(V, ay.w, &d.wy)) || (rc = upload(V, ax.V, &d.Evx)) ||
+        (rc = upload(V, ax.D, &d.Edx)) || (rc = upload(V, ay.V, &d.Evy)) || (rc = upload(V, ay.D, &d.Edy))) {
+        delete V;
+        return rc;
+    }
+    // own copy of the coefficient (compact) and the element scratch
+    const long rows = (long)x->n * qx, cols = (long)y->n * qy;
+    double* a = nullptr;
+    double* ye = nullptr;
+    if (dmalloc(&a, (size_t)rows * cols) != hipSuccess ||
+        dmalloc(&ye, (size_t)x->n * y->n * (x->p + 1) * (y->p + 1)) != hipSuccess) {
+        (void)hipFree(a);
+        delete V;
+        return HPADI_ENOMEM;
+    }
+    V->allocs.push_back(a);
+    V->allocs.push_back(ye);
+    if (hpadi::launch_copy2d(a_dev, lda, a, cols, (int)rows, (int)cols, V->stream) != hipSuccess ||
+        hipStreamSynchronize(V->stream) != hipSuccess) {
+        delete V;
+        return HPADI_EHIP;
+    }
+    d.a = a;
+    d.lda = cols;
+    d.Ye = ye;
+    *out = V;
+    return HPADI_OK;
+}
+
+int hpadi_varcoef_apply(hpadi_varcoef V, const double* U, int ldu, double* Y, int ldy) {
+    if (!V || !U || !Y || ldu < V->Ny || ldy < V->Ny) return HPADI_EINVAL;
+    return hpadi::launch_vc_apply(V->dev, U, ldu, Y, ldy, V->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+}
+
+void hpadi_varcoef_destroy(hpadi_varcoef V) { delete V; }
+
+int hpadi_fcg_solve(hpadi_varcoef V, hpadi_plan precond, const double* b, int ldb, double* x, int ldx, double tol,
+                    int maxit, int truncation, double* res_hist, int hist_len, hpadi_krylov_stats* stats) {
+    if (!V || !b || !x || ldb < V->Ny || ldx < V->Ny || !(tol > 0.0) || maxit < 0 || truncation < 0 ||
+        truncation > 4)
+        return HPADI_EINVAL;
+    if (precond && (precond->dx.op.N != V->Nx || precond->dy.op.N != V->Ny)) return HPADI_EINVAL;
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = ensure_work(V, truncation);
+    if (rc != HPADI_OK) return rc;
+    hipStream_t s = V->stream;
+    const int Nx = V->Nx, Ny = V->Ny;
+    const long n = (long)Nx * Ny;
+    hpadi_krylov_stats st{};
+    // compact copy of b lives in q[last] for the true residual; x starts at 0
+    double* bc = V->q.back();
+    double* xc = V->d.back();
+    if (hpadi::launch_copy2d(b, ldb, bc, Ny, Nx, Ny, s) != hipSuccess ||
+        hipMemsetAsync(xc, 0, n * sizeof(double), s) != hipSuccess ||
+        hipMemcpyAsync(V->r, bc, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return HPADI_EHIP;
+    double bb;
+    if ((rc = dots(V, bc, {bc}, &bb)) != HPADI_OK) return rc;
+    const double bn = std::sqrt(bb);
+    if (res_hist && hist_len > 0) res_hist[0] = 1.0;
+    auto precondition = [&]() -> int {
+        // z = P r (ADI solve of the constant-coefficient operator), or z = r
+        if (!precond)
+            return hipMemcpyAsync(V->z, V->r, n * sizeof(double), hipMemcpyDeviceToDevice, s) == hipSuccess
+                       ? HPADI_OK
+                       : HPADI_EHIP;
+        if (precond->stream != s && hipStreamSynchronize(s) != hipSuccess) return HPADI_EHIP;
+        hpadi_stats ps{};
+        int r2 = hpadi_solve(precond, V->r, Ny, V->z, Ny, &ps);
+        if (r2 != HPADI_OK && r2 != HPADI_ENOCONV) return r2;
+        if (precond->stream != s && hipStreamSynchronize(precond->stream) != hipSuccess) return HPADI_EHIP;
+        st.precond_calls++;
+        return HPADI_OK;
+    };
+    const int m = truncation;
+    int k = 0;
+    bool converged = bn == 0.0;
+    double rel = converged ? 0.0 : 1.0;
+    double rz_old = 0.0;
+    std::vector<double> dq_hist(std::max(m, 1) + 1, 0.0);
+    const int ring = std::max(m, 1);
+    while (!converged && k < maxit) {
+        if ((rc = precondition()) != HPADI_OK) return rc;
+        double* dk = V->d[k % ring];
+        double* qk = V->q[k % ring];
+        if (m == 0) {
+            // PCG: d = z + beta d, beta = (r.z) / (r_old.z_old)
+            double rz;
+            if ((rc = dots(V, V->r, {V->z}, &rz)) != HPADI_OK) return rc;
+            const double beta = k == 0 ? 0.0 : rz / rz_old;
+            rz_old = rz;
+            if (hpadi::launch_xpby(dk, V->z, beta, n, s) != hipSuccess) return HPADI_EHIP;
+        } else {
+            // FCG(m): d = z - sum_{i in window} (z.q_i / d_i.q_i) d_i
+            const int nw = std::min(k, m);
+            double c[4] = {0, 0, 0, 0};
+            if (nw > 0) {
+                hpadi::MultiB mb{};
+                mb.nb = nw;
+                for (int i = 0; i < nw; ++i) mb.b[i] = V->q[(k - 1 - i) % ring];
+                if (hpadi::launch_multidot(V->z, mb, n, V->part, V->dots, s) != hipSuccess ||
+                    hipMemcpyAsync(V->dots_host, V->dots, nw * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return HPADI_EHIP;
+                for (int i = 0; i < nw; ++i) c[i] = -V->dots_host[i] / dq_hist[(k - 1 - i) % ring];
+            }
+            // the oldest direction of the ring is overwritten by d_k: form d_k in z first
+            if (nw > 0) {
+                hpadi::MultiB xs{};
+                hpadi::Coefs cc{};
+                xs.nb = nw;
+                for (int i = 0; i < nw; ++i) {
+                    xs.b[i] = V->d[(k - 1 - i) % ring];
+                    cc.c[i] = c[i];
+                }
+                if (hpadi::launch_axpys(V->z, xs, cc, n, s) != hipSuccess) return HPADI_EHIP;
+            }
+            if (hipMemcpyAsync(dk, V->z, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return HPADI_EHIP;
+        }
+        // q = A d; alpha = d.r / d.q
+        if (hpadi::launch_vc_apply(V->dev, dk, Ny, qk, Ny, s) != hipSuccess) return HPADI_EHIP;
+        double dd[2];
+        if ((rc = dots(V, dk, {qk, V->r}, dd)) != HPADI_OK) return rc;
+        const double dq = dd[0];
+        if (!(dq > 0.0) || !std::isfinite(dq)) {
+            rc = HPADI_ENOTSPD;
+            break;
+        }
+        dq_hist[k % ring] = dq;
+        const double alpha = (m == 0 ? rz_old : dd[1]) / dq;
+        if ((rc = axpy(V, xc, alpha, dk)) != HPADI_OK || (rc = axpy(V, V->r, -alpha, qk)) != HPADI_OK) return rc;
+        ++k;
+        double rr;
+        if ((rc = dots(V, V->r, {V->r}, &rr)) != HPADI_OK) return rc;
+        rel = std::sqrt(std::max(rr, 0.0)) / bn;
+        if (res_hist && k < hist_len) res_hist[k] = rel;
+        if (!std::isfinite(rel)) break;
+        if (rel <= tol) converged = true;
+    }
+    if (rc != HPADI_OK && rc != HPADI_ENOTSPD) return rc;
+    // true residual b - A x, and x to the caller's layout
+    double* tr = V->z;
+    if (hpadi::launch_vc_apply(V->dev, xc, Ny, tr, Ny, s) != hipSuccess) return HPADI_EHIP;
+    if (axpy(V, tr, -1.0, bc) != HPADI_OK) return HPADI_EHIP;
+    double trr = 0.0;
+    if (dots(V, tr, {tr}, &trr) != HPADI_OK) return HPADI_EHIP;
+    if (hpadi::launch_copy2d(xc, Ny, x, ldx, Nx, Ny, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return HPADI_EHIP;
+    st.iters = k;
+    st.rel_res = rel;
+    st.true_rel_res = bn > 0 ? std::sqrt(std::max(trr, 0.0)) / bn : 0.0;
+    st.status = rc != HPADI_OK ? rc : (converged ? HPADI_OK : HPADI_ENOCONV);
+    st.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return st.status;
+}
+
+}  // extern "C"

@@ -25,13 +25,19 @@ class hpadi_stats(ctypes.Structure):
     _fields_ = [("J", ctypes.c_int), ("rounds", ctypes.c_int), ("iters", ctypes.c_int),
                 ("status", ctypes.c_int), ("interval", ctypes.c_double * 4),
                 ("est_rel_err", ctypes.c_double), ("res_rel", ctypes.c_double),
-                ("t_ms", ctypes.c_double * 4)]
+                ("fp32_rounds", ctypes.c_int), ("reserved0", ctypes.c_int), ("t_ms", ctypes.c_double * 3)]
 
 
 class hpadi_options(ctypes.Structure):
     _fields_ = [("inner_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
                 ("lines_per_block", ctypes.c_int),
-                ("fixed_rounds", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("fixed_rounds", ctypes.c_int), ("fp32_rounds", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+
+
+class hpadi_krylov_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("precond_calls", ctypes.c_int),
+                ("reserved0", ctypes.c_int), ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("t_ms", ctypes.c_double), ("reserved", ctypes.c_double * 3)]
 
 
 # name -> (restype, argtypes), in the order of include/hpadi.h
@@ -58,6 +64,15 @@ SIGNATURES = {
                                    ctypes.POINTER(hpadi_stats)]),
     "hpadi_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "hpadi_plan_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_varcoef_grid": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, ctypes.c_int]),
+    "hpadi_varcoef_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_varcoef_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_int]),
+    "hpadi_varcoef_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_fcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                       _c_double_p, ctypes.c_int, ctypes.POINTER(hpadi_krylov_stats)]),
     "hpadi_plan_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hpadi_plan_timing_read": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, _c_int_p]),
     "hpadi_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -220,14 +235,54 @@ def hpadi_plan_destroy(plan):
     lib().hpadi_plan_destroy(plan)
 
 
+def hpadi_varcoef_grid(op, n, p):
+    import numpy as np
+    q = p + 2
+    x = np.zeros(n * q)
+    w = np.zeros(n * q)
+    check(lib().hpadi_varcoef_grid(op, _dptr(x), _dptr(w), n * q), "hpadi_varcoef_grid")
+    return x, w
+
+
+def hpadi_varcoef_create(x, y, a, stream=None):
+    ap, lda = _tptr(a)
+    h = ctypes.c_void_p()
+    check(lib().hpadi_varcoef_create(x, y, ap, lda, _stream_handle(stream), ctypes.byref(h)),
+          "hpadi_varcoef_create")
+    return h
+
+
+def hpadi_varcoef_apply(vc, U, Y):
+    up, ldu = _tptr(U)
+    yp, ldy = _tptr(Y)
+    check(lib().hpadi_varcoef_apply(vc, up, ldu, yp, ldy), "hpadi_varcoef_apply")
+
+
+def hpadi_varcoef_destroy(vc):
+    lib().hpadi_varcoef_destroy(vc)
+
+
+def hpadi_fcg_solve(vc, precond, b, x, tol, maxit, truncation, hist_len=0, raise_on_noconv=True):
+    import numpy as np
+    bp, ldb = _tptr(b)
+    xp, ldx = _tptr(x)
+    hist = np.zeros(max(hist_len, 1))
+    st = hpadi_krylov_stats()
+    rc = lib().hpadi_fcg_solve(vc, precond, bp, ldb, xp, ldx, float(tol), int(maxit), int(truncation),
+                               _dptr(hist) if hist_len > 0 else None, int(hist_len), ctypes.byref(st))
+    if rc != HPADI_OK and (raise_on_noconv or rc != HPADI_ENOCONV):
+        raise HpadiError(rc, "hpadi_fcg_solve")
+    return st, hist[:min(st.iters + 1, hist_len)] if hist_len > 0 else None
+
+
 def hpadi_plan_timing(plan, enable):
     check(lib().hpadi_plan_timing(plan, int(bool(enable))), "hpadi_plan_timing")
 
 
 def hpadi_plan_timing_read(plan):
-    ms = (ctypes.c_double * 3)()
-    by = (ctypes.c_double * 3)()
-    ct = (ctypes.c_int * 3)()
+    ms = (ctypes.c_double * 6)()
+    by = (ctypes.c_double * 6)()
+    ct = (ctypes.c_int * 6)()
     check(lib().hpadi_plan_timing_read(plan, ms, by, ct), "hpadi_plan_timing_read")
     return list(ms), list(by), list(ct)
 
@@ -301,6 +356,50 @@ class Plan:
     def close(self):
         if self.handle is not None:
             hpadi_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class VarCoef:
+    """Variable-coefficient operator -div(a grad u) on the bases of x and y."""
+
+    def __init__(self, x: Op1D, y: Op1D, a, stream=None):
+        self.x, self.y = x, y
+        qx, qy = x.p + 2, y.p + 2
+        if tuple(a.shape) != (x.n * qx, y.n * qy):
+            raise ValueError(f"a must be {x.n * qx} x {y.n * qy} (Gauss grid)")
+        self.handle = hpadi_varcoef_create(x.handle, y.handle, a, stream)
+
+    @staticmethod
+    def grid(op: Op1D):
+        return hpadi_varcoef_grid(op.handle, op.n, op.p)
+
+    def apply(self, U):
+        import torch
+        if tuple(U.shape) != (self.x.N, self.y.N):
+            raise ValueError(f"U must be {self.x.N} x {self.y.N}")
+        Y = torch.empty_like(U)
+        hpadi_varcoef_apply(self.handle, U, Y)
+        return Y
+
+    def solve(self, b, precond: "Plan" = None, tol=1e-10, maxit=500, truncation=1, hist_len=0,
+              raise_on_noconv=True):
+        import torch
+        if tuple(b.shape) != (self.x.N, self.y.N):
+            raise ValueError(f"b must be {self.x.N} x {self.y.N}")
+        x = torch.empty_like(b)
+        st, hist = hpadi_fcg_solve(self.handle, precond.handle if precond is not None else None, b, x, tol,
+                                   maxit, truncation, hist_len, raise_on_noconv)
+        return x, st, hist
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            hpadi_varcoef_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

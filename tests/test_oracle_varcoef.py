@@ -1,0 +1,154 @@
+"""Pins of the variable-coefficient oracle (oracle/varcoef.py).
+
+* a = 1 reduces to K (x) M + M (x) K, pinned elsewhere against App. A;
+* a separable polynomial of degree <= 3 per variable (integrated exactly by the
+  q = p + 2 point rule) against 1D weighted matrices integrated by adaptive
+  quadrature of the Jacobi-form basis functions (no code shared with the
+  operator);
+* symmetry and positivity of the discrete operator for a random field;
+* CG against a dense direct solve; PCG with the exact inverse as
+  preconditioner converges in one step; FCG(1) reproduces the PCG iterates for
+  a fixed SPD preconditioner.
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+
+import workloads
+from oracle import adi as oadi
+from oracle import basis as obasis
+from oracle import varcoef as ovc
+
+
+def ops(n, p, bc, lo=0.0, hi=1.0):
+    return obasis.assemble(obasis.make_basis(n, p, lo, hi, bc))
+
+
+def test_gauss_grid_weights_and_points():
+    B = obasis.make_basis(3, 5, -1.0, 2.0, "dirichlet")
+    g = ovc.gauss_grid(B)
+    assert g.q == 7
+    assert abs(g.w.sum() - 3.0) < 1e-14
+    for e in range(3):
+        xe = g.x[e * g.q:(e + 1) * g.q]
+        assert np.all((xe > B.x[e]) & (xe < B.x[e + 1]))
+    # exactness for a degree 2q-1 monomial on one element
+    assert abs(np.sum(g.wt * g.t ** 12) - 2.0 / 13.0) < 1e-14
+
+
+def test_local_functions_match_jacobi_form():
+    p = 9
+    t = np.linspace(-0.97, 0.93, 17)
+    V, D = ovc.local_functions(p, t)
+    for k in range(p - 1):
+        poly = obasis._bubble_poly(k)
+        assert np.allclose(V[:, 2 + k], poly(t), atol=1e-13)
+        assert np.allclose(D[:, 2 + k], poly.deriv()(t), atol=1e-12)
+    assert np.allclose(V[:, 0] + V[:, 1], 1.0)
+
+
+@pytest.mark.parametrize("n,p,bc", [(2, 4, "dirichlet"), (3, 6, "neumann"), (4, 3, "dirichlet")])
+def test_unit_coefficient_is_constant_operator(n, p, bc):
+    ox, oy = ops(n, p, bc), ops(n + 1, p + 1, bc)
+    gx, gy = ovc.gauss_grid(ox.basis), ovc.gauss_grid(oy.basis)
+    op = ovc.VarCoefOperator(ox.basis, oy.basis, np.ones((gx.x.size, gy.x.size)))
+    U = np.random.default_rng(1).standard_normal((ox.basis.N, oy.basis.N))
+    Y = op.apply(U)
+    Yref = oadi.apply_operator(ox, oy, 0.0, U)
+    assert np.abs(Y - Yref).max() <= 1e-12 * np.abs(Yref).max()
+
+
+def _weighted_1d(B, f):
+    """K_f[i,j] = int f phi_i' phi_j', M_f[i,j] = int f phi_i phi_j by adaptive
+    quadrature per element of the Jacobi-form functions."""
+    hat_pos = {v: i for i, v in enumerate(B.hat_vertices())}
+    N = B.N
+    K, M = np.zeros((N, N)), np.zeros((N, N))
+    polys = [obasis._bubble_poly(m) for m in range(B.p - 1)]
+    for e in range(B.n):
+        a, b = B.x[e], B.x[e + 1]
+        de = b - a
+        funcs = []
+        for v, val, dval in ((e, lambda t: (1 - t) / 2, lambda t: -1.0 / de),
+                             (e + 1, lambda t: (1 + t) / 2, lambda t: 1.0 / de)):
+            if v in hat_pos:
+                funcs.append((hat_pos[v], val, dval))
+        for m in range(B.p - 1):
+            pm, dm = polys[m], polys[m].deriv()
+            funcs.append((int(B.bubble_index(m, e)), (lambda t, pm=pm: pm(t)),
+                          (lambda t, dm=dm: dm(t) * 2.0 / de)))
+        xt = lambda t: a + (t + 1) * de / 2
+        for (i, vi, di) in funcs:
+            for (j, vj, dj) in funcs:
+                M[i, j] += integrate.quad(lambda t: f(xt(t)) * vi(t) * vj(t), -1, 1, epsabs=1e-14, epsrel=1e-13, limit=200)[0] * de / 2
+                K[i, j] += integrate.quad(lambda t: f(xt(t)) * di(t) * dj(t), -1, 1, epsabs=1e-14, epsrel=1e-13, limit=200)[0] * de / 2
+    return K, M
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
+def test_separable_cubic_coefficient_against_adaptive_quadrature(bc):
+    f = lambda x: 1.0 + x + 0.5 * x ** 3
+    g = lambda y: 2.0 - y ** 2
+    Bx = obasis.make_basis(2, 4, 0.0, 1.0, bc)
+    By = obasis.make_basis(2, 3, -1.0, 0.5, bc)
+    gx, gy = ovc.gauss_grid(Bx), ovc.gauss_grid(By)
+    op = ovc.VarCoefOperator(Bx, By, np.outer(f(gx.x), g(gy.x)))
+    Kf, Mf = _weighted_1d(Bx, f)
+    Kg, Mg = _weighted_1d(By, g)
+    ref = np.kron(Kf, Mg) + np.kron(Mf, Kg)
+    A = op.dense()
+    assert np.abs(A - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_random_field_operator_is_spd():
+    Bx = obasis.make_basis(3, 4, 0.0, 1.0, "dirichlet")
+    gx = ovc.gauss_grid(Bx)
+    a = workloads.grf_coefficient(gx.x, gx.x, seed=5)
+    assert a.min() > 1.0
+    A = ovc.VarCoefOperator(Bx, Bx, a).dense()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+
+
+def _small_problem(seed=7, n=3, p=5):
+    Bx = obasis.make_basis(n, p, 0.0, 1.0, "dirichlet")
+    gx = ovc.gauss_grid(Bx)
+    a = workloads.grf_coefficient(gx.x, gx.x, seed=seed)
+    op = ovc.VarCoefOperator(Bx, Bx, a)
+    b = np.random.default_rng(seed).standard_normal((Bx.N, Bx.N))
+    return Bx, op, b
+
+
+def test_cg_matches_direct_solve():
+    Bx, op, b = _small_problem()
+    A = op.dense()
+    x_ref = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    res = ovc.pcg(op.apply, lambda r: r, b, 1e-13, 500)
+    assert res.converged and res.true_rel_res <= 1e-12
+    assert np.abs(res.x - x_ref).max() <= 1e-9 * np.abs(x_ref).max()
+
+
+def test_pcg_with_exact_inverse_takes_one_step():
+    Bx = obasis.make_basis(3, 5, 0.0, 1.0, "dirichlet")
+    gx = ovc.gauss_grid(Bx)
+    op = ovc.VarCoefOperator(Bx, Bx, 3.0 * np.ones((gx.x.size, gx.x.size)))
+    A = op.dense()
+    Ainv = np.linalg.inv(A)
+    b = np.random.default_rng(3).standard_normal((Bx.N, Bx.N))
+    res = ovc.pcg(op.apply, lambda r: (Ainv @ r.reshape(-1)).reshape(r.shape), b, 1e-12, 10)
+    assert res.iters == 1 and res.converged
+
+
+@pytest.mark.parametrize("m", [1, 2])
+def test_fcg_reproduces_pcg_iterates(m):
+    Bx, op, b = _small_problem(seed=11)
+    ox = obasis.assemble(Bx)
+    A0 = ovc.VarCoefOperator(Bx, Bx, np.ones_like(op.a)).dense()
+    A0inv = np.linalg.inv(A0)
+    P = lambda r: (A0inv @ r.reshape(-1)).reshape(r.shape)
+    r1 = ovc.pcg(op.apply, P, b, 1e-11, 100, keep_iterates=True)
+    r2 = ovc.fcg(op.apply, P, b, 1e-11, 100, m=m, keep_iterates=True)
+    assert r1.iters == r2.iters
+    for x1, x2 in zip(r1.iterates, r2.iterates):
+        assert np.abs(x1 - x2).max() <= 1e-8 * max(1e-300, np.abs(r1.x).max())
+    assert r2.true_rel_res <= 1e-10

@@ -122,3 +122,39 @@ def manufactured_sin(omega2: float):
     def fx(x):
         return np.sin(math.pi * x)
     return fx, fx, 2.0 * math.pi ** 2 + omega2
+
+
+# ---------------------------------------------------------------------------
+# Variable coefficients a(x, y) for -div(a grad u) = f, sampled at given points
+# (the tensor grid of quadrature points of the discretisation).
+# ---------------------------------------------------------------------------
+
+def _se_factor(x: np.ndarray, ell: float, jitter: float) -> np.ndarray:
+    """A square root S (S S^T = C) of the squared-exponential covariance
+    C_ij = exp(-(x_i - x_j)^2 / (2 ell^2)) + jitter delta_ij, by a symmetric
+    eigendecomposition (negative rounding-level eigenvalues clipped)."""
+    d = x[:, None] - x[None, :]
+    C = np.exp(-0.5 * (d / ell) ** 2) + jitter * np.eye(x.size)
+    lam, V = np.linalg.eigh(C)
+    return V * np.sqrt(np.clip(lam, 0.0, None))[None, :]
+
+
+def grf_coefficient(xs: np.ndarray, ys: np.ndarray, seed: int, ell: float = 0.2,
+                    jitter: float = 1e-10) -> np.ndarray:
+    """a = 1 + exp(g)/2 on the tensor grid xs x ys, g a centred Gaussian field
+    with separable squared-exponential covariance (length scale ell, variance 1),
+    sampled as g = S_x Z S_y^T with Z ~ N(0, 1) i.i.d. (default_rng(seed))."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((xs.size, ys.size))
+    g = _se_factor(np.asarray(xs, float), ell, jitter) @ Z @ _se_factor(np.asarray(ys, float), ell, jitter).T
+    return 1.0 + 0.5 * np.exp(g)
+
+
+def singular_coefficient(xs: np.ndarray, ys: np.ndarray, x0: float) -> np.ndarray:
+    """a = |x - x0|^(1/2) + 1/10 on the tensor grid xs x ys."""
+    return np.repeat((np.sqrt(np.abs(np.asarray(xs, float) - x0)) + 0.1)[:, None], len(ys), axis=1)
+
+
+def singular_x0(seed: int) -> float:
+    """x0 ~ U(0, 1) for the singular coefficient family."""
+    return float(np.random.default_rng(seed).uniform(0.0, 1.0))
