@@ -194,24 +194,77 @@ typedef struct {
     int iters;            /* Krylov iterations (operator applications) */
     int status;           /* HPADI_OK, HPADI_ENOCONV or HPADI_ENOTSPD */
     int precond_calls;    /* preconditioner applications */
-    int reserved0;
+    int corrections;      /* learned corrections accepted (0 without a network) */
     double rel_res;       /* ||r_k|| / ||b|| of the recurrence residual at exit */
     double true_rel_res;  /* ||b - A_a x|| / ||b||, recomputed in FP64 at exit */
     double t_ms;          /* host wall time of the call */
     double reserved[3];
 } hpadi_krylov_stats;
 
+/* ---- Learned correction (an addition to Sec. 7's ADI-preconditioned CG) -- */
+
+/* A small convolutional network on the coefficient image: per dimension the
+ * coefficients are laid out element by element (the element's left-vertex hat,
+ * then W_0 .. W_{p-2}; one trailing slot for the last vertex), an image of
+ * (n_x p_x + 1) x (n_y p_y + 1) pixels.  Channels 3 -> 32 -> 32 -> 32 -> 1, 3x3
+ * convolutions with zero padding, tanh-form GELU after the hidden layers; BF16
+ * activations and weights on the matrix cores with FP32 accumulation, FP32
+ * master parameters.  Inside the Krylov loop the preconditioned residual is
+ * corrected as z <- z + s_z NN([z/s_z, r/s_r, log a]) (s: root-mean-square
+ * values); a correction that is not finite or makes z.r <= 0 is dropped and
+ * the plain z is used. */
+typedef struct hpadi_net_s* hpadi_net;
+
+/* Number of FP32 parameters: W0[3][3][3][32] b0[32] W1[3][3][32][32] b1[32]
+ * W2[3][3][32][32] b2[32] W3[3][3][32][1] b3[1], in that order (W[dy][dx][c_in][c_out]). */
+int hpadi_net_num_params(void);
+/* params: host array of hpadi_net_num_params() floats, or NULL for a seeded
+ * initialisation (normal, std sqrt(2 / fan_in), last layer scaled by 1/10,
+ * zero biases).  hip_stream: a hipStream_t or NULL. */
+int hpadi_net_create(const float* params, unsigned long long seed, void* hip_stream, hpadi_net* out);
+int hpadi_net_get_params(hpadi_net net, float* params);
+int hpadi_net_set_params(hpadi_net net, const float* params);
+/* out = NN(x): x FP32 device [B][H][W][3], out FP32 device [B][H][W]. */
+int hpadi_net_forward(hpadi_net net, const float* x_dev, int B, int H, int W, float* out_dev);
+/* Loss of a batch and its gradient with respect to the parameters (host copy),
+ * without updating:  L = (1/B) sum_b sum_p w (zn + NN(x) - t)^2 / sum_p w t^2.
+ * x [B][H][W][3], zn, t, w [B][H][W]: FP32 device.  W must be a multiple of 16.
+ * grad may be NULL. */
+int hpadi_net_loss_grad(hpadi_net net, const float* x_dev, const float* zn_dev, const float* t_dev,
+                        const float* w_dev, int B, int H, int W, double* loss, float* grad);
+/* Adam training (beta 0.9, 0.999, eps 1e-8) on npairs crops of c x c pixels
+ * (arrays laid out as for hpadi_net_loss_grad with B = npairs): steps steps of
+ * batch crops drawn uniformly with a counter-based generator from seed.
+ * loss_hist (host, may be NULL) receives the loss of each step. */
+int hpadi_net_train(hpadi_net net, const float* X_dev, const float* ZN_dev, const float* T_dev, const float* W_dev,
+                    int npairs, int c, int batch, int steps, double lr, unsigned long long seed, float* loss_hist);
+/* Training pairs from the method: plain preconditioned CG (truncation 0) on
+ * A_a x = b from x = 0; after the preconditioner of iteration k the images
+ * [z/s_z, r/s_r, log a], zn = z/s_z, t = (xstar - x_k)/s_z and the slot weights
+ * w (diagonal of M_x times diagonal of M_y) are formed and crops_per_iter
+ * random c x c crops of them are appended to X (3 ch), ZN, T, Wt (FP32 device,
+ * capacity cap crops).  xstar: the converged solution (device, ldxs).  Stops
+ * after max_iters iterations, at convergence (tol) or when cap crops are
+ * stored; *count = crops stored. */
+int hpadi_net_pairs(hpadi_varcoef vc, hpadi_plan precond, const double* b_dev, int ldb, const double* xstar_dev,
+                    int ldxs, double tol, int max_iters, int c, int crops_per_iter, unsigned long long seed,
+                    float* X_dev, float* ZN_dev, float* T_dev, float* W_dev, int cap, int* count);
+void hpadi_net_destroy(hpadi_net net);
+
 /* Solve A_a x = b from x = 0 until ||r_k||_2 / ||b||_2 <= tol (FP64 vectors).
  * truncation = 0: preconditioned CG; 1..4: flexible CG keeping that many
  * previous directions (each new direction is the preconditioned residual made
  * A_a-orthogonal to them; alpha = d.r / d.A d).  precond: an ADI plan whose
  * solve is the preconditioner (its N_x, N_y must match; typically omega2 = 0,
- * tol 1e-4), or NULL for none.  res_hist (host, may be NULL) receives the
- * relative recurrence residual of iterates 0..min(iters, hist_len-1).
- * Synchronises the stream once per dot product.  ENOCONV after maxit
- * iterations (x holds the last iterate); ENOTSPD if d.A d <= 0. */
-int hpadi_fcg_solve(hpadi_varcoef vc, hpadi_plan precond, const double* b_dev, int ldb, double* x_dev, int ldx,
-                    double tol, int maxit, int truncation, double* res_hist, int hist_len,
+ * tol 1e-4), or NULL for none.  net: a learned correction applied after each
+ * preconditioner application (NULL for none; use truncation >= 1 with it, the
+ * corrected preconditioner is not a fixed linear map).  res_hist (host, may be
+ * NULL) receives the relative recurrence residual of iterates
+ * 0..min(iters, hist_len-1).  Synchronises the stream once per dot product.
+ * ENOCONV after maxit iterations (x holds the last iterate); ENOTSPD if
+ * d.A d <= 0. */
+int hpadi_fcg_solve(hpadi_varcoef vc, hpadi_plan precond, hpadi_net net, const double* b_dev, int ldb, double* x_dev,
+                    int ldx, double tol, int maxit, int truncation, double* res_hist, int hist_len,
                     hpadi_krylov_stats* stats);
 
 /* ---- Measurement ------------------------------------------------------- */

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhpadi.so")
 
-SOURCES = ["host.cpp", "krylov.cpp", "kernels.hip", "sweep.hip", "sweep_uni.hip", "varcoef.hip"]
+SOURCES = ["host.cpp", "krylov.cpp", "net.cpp", "kernels.hip", "sweep.hip", "sweep_uni.hip", "varcoef.hip", "net.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -57,7 +57,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     import tempfile
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
     with tempfile.TemporaryDirectory(prefix="hpadi_build_") as tmpdir:
-        objs = [os.path.join(tmpdir, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+        objs = [os.path.join(tmpdir, src + ".o") for src in SOURCES]
         with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
             for f in [ex.submit(_compile, src, obj, verbose) for src, obj in zip(SOURCES, objs)]:
                 f.result()

@@ -13,6 +13,7 @@
 #include "host_internal.h"
 #include "hpadi.h"
 #include "krylov.h"
+#include "krylov_internal.h"
 
 using hpadi_host::dmalloc;
 
@@ -120,32 +121,6 @@ void make_axis(const hpadi_op1d_s& o, VcAxis& A) {
 
 }  // namespace
 
-struct hpadi_varcoef_s {
-    hpadi::VarCoefDev dev{};
-    hipStream_t stream = nullptr;
-    int Nx = 0, Ny = 0;
-    std::vector<void*> allocs;
-    // Krylov work (allocated on first use): r, z, x-copy, (d, q) x (m + 1), partials, dots
-    int mwork = -1;
-    double* r = nullptr;
-    double* z = nullptr;
-    std::vector<double*> d, q;
-    double* part = nullptr;
-    double* dots = nullptr;
-    double* dots_host = nullptr;
-    ~hpadi_varcoef_s() {
-        if (stream) (void)hipStreamSynchronize(stream);
-        for (void* p : allocs) (void)hipFree(p);
-        for (double* p : d) (void)hipFree(p);
-        for (double* p : q) (void)hipFree(p);
-        (void)hipFree(r);
-        (void)hipFree(z);
-        (void)hipFree(part);
-        (void)hipFree(dots);
-        if (dots_host) (void)hipHostFree(dots_host);
-    }
-};
-
 namespace {
 
 template <typename T>
@@ -162,7 +137,7 @@ int upload(hpadi_varcoef_s* V, const std::vector<T>& h, const T** out) {
 int ensure_work(hpadi_varcoef_s* V, int m) {
     const size_t n = (size_t)V->Nx * V->Ny;
     if (!V->r) {
-        if (dmalloc(&V->r, n) != hipSuccess || dmalloc(&V->z, n) != hipSuccess ||
+        if (dmalloc(&V->r, n) != hipSuccess || dmalloc(&V->z, n) != hipSuccess || dmalloc(&V->zs, n) != hipSuccess ||
             dmalloc(&V->part, 4 * (size_t)hpadi::dot_parts()) != hipSuccess || dmalloc(&V->dots, 8) != hipSuccess)
             return HPADI_ENOMEM;
         if (hipHostMalloc((void**)&V->dots_host, 8 * sizeof(double)) != hipSuccess) return HPADI_ENOMEM;
@@ -268,6 +243,13 @@ int hpadi_varcoef_create(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int ld
     d.a = a;
     d.lda = cols;
     d.Ye = ye;
+    V->opx = *x;
+    V->opy = *y;
+    V->a_host.resize((size_t)rows * cols);
+    if (hipMemcpy(V->a_host.data(), a, V->a_host.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        delete V;
+        return HPADI_EHIP;
+    }
     *out = V;
     return HPADI_OK;
 }
@@ -279,12 +261,24 @@ int hpadi_varcoef_apply(hpadi_varcoef V, const double* U, int ldu, double* Y, in
 
 void hpadi_varcoef_destroy(hpadi_varcoef V) { delete V; }
 
-int hpadi_fcg_solve(hpadi_varcoef V, hpadi_plan precond, const double* b, int ldb, double* x, int ldx, double tol,
-                    int maxit, int truncation, double* res_hist, int hist_len, hpadi_krylov_stats* stats) {
+int hpadi_fcg_solve(hpadi_varcoef V, hpadi_plan precond, hpadi_net net, const double* b, int ldb, double* x, int ldx,
+                    double tol, int maxit, int truncation, double* res_hist, int hist_len, hpadi_krylov_stats* stats) {
+    return hpadi_host::fcg_core(V, precond, net, b, ldb, x, ldx, tol, maxit, truncation, res_hist, hist_len, stats,
+                                hpadi_host::KrylovObserver());
+}
+
+}  // extern "C"
+
+namespace hpadi_host {
+
+int fcg_core(hpadi_varcoef_s* V, hpadi_plan precond, hpadi_net net, const double* b, int ldb, double* x, int ldx,
+             double tol, int maxit, int truncation, double* res_hist, int hist_len, hpadi_krylov_stats* stats,
+             const KrylovObserver& observe) {
     if (!V || !b || !x || ldb < V->Ny || ldx < V->Ny || !(tol > 0.0) || maxit < 0 || truncation < 0 ||
         truncation > 4)
         return HPADI_EINVAL;
     if (precond && (precond->dx.op.N != V->Nx || precond->dy.op.N != V->Ny)) return HPADI_EINVAL;
+    if (net && ensure_slots(V) != HPADI_OK) return HPADI_ENOMEM;
     const auto t0 = std::chrono::steady_clock::now();
     int rc = ensure_work(V, truncation);
     if (rc != HPADI_OK) return rc;
@@ -326,6 +320,12 @@ int hpadi_fcg_solve(hpadi_varcoef V, hpadi_plan precond, const double* b, int ld
     const int ring = std::max(m, 1);
     while (!converged && k < maxit) {
         if ((rc = precondition()) != HPADI_OK) return rc;
+        if (net) {
+            bool applied = false;
+            if ((rc = net_correct(net, V, V->r, V->z, &applied)) != HPADI_OK) return rc;
+            if (applied) st.corrections++;
+        }
+        if (observe && (rc = observe(k, V->r, V->z, xc)) != HPADI_OK) return rc;
         double* dk = V->d[k % ring];
         double* qk = V->q[k % ring];
         if (m == 0) {
@@ -401,4 +401,65 @@ int hpadi_fcg_solve(hpadi_varcoef V, hpadi_plan precond, const double* b, int ld
     return st.status;
 }
 
-}  // extern "C"
+
+int ensure_slots(hpadi_varcoef_s* V) {
+    if (V->sx) return HPADI_OK;
+    const hpadi_op1d_s* ops[2] = {&V->opx, &V->opy};
+    std::vector<int> slot[2];
+    std::vector<int> gidx[2];      // Gauss index (e q + i) of each slot
+    std::vector<float> wts[2];
+    for (int a = 0; a < 2; ++a) {
+        const hpadi_op1d_s& o = *ops[a];
+        const int S = o.n * o.p + 1, q = o.p + 2;
+        std::vector<double> t, w;
+        gauss_legendre(q, t, w);
+        slot[a].assign(S, -1);
+        gidx[a].assign(S, 0);
+        wts[a].assign(S, 0.0f);
+        for (int s = 0; s < S; ++s) {
+            const int e = std::min(s / o.p, o.n - 1);
+            const int j = s - e * o.p;  // 0 = left vertex, p = right vertex (last slot), else bubble j-1
+            double xi;
+            if (j == 0 || j == o.p) {
+                const int v = e + (j == o.p ? 1 : 0);
+                if (o.vertex_is_hat(v)) {
+                    slot[a][s] = o.hat_of_vertex(v);
+                    const double dl = v > 0 ? o.delta[v - 1] : 0.0, dr = v < o.n ? o.delta[v] : 0.0;
+                    wts[a][s] = (float)((dl + dr) / 3.0);
+                }
+                xi = j == 0 ? -1.0 : 1.0;
+            } else {
+                const int m = j - 1;
+                slot[a][s] = o.bubble(m, e);
+                wts[a][s] = (float)(2.0 * o.delta[e] / ((2.0 * m + 1) * (2.0 * m + 3) * (2.0 * m + 5)));
+                xi = -1.0 + 2.0 * j / o.p;
+            }
+            int best = 0;
+            for (int i = 1; i < q; ++i)
+                if (std::fabs(t[i] - xi) < std::fabs(t[best] - xi)) best = i;
+            gidx[a][s] = e * q + best;
+        }
+    }
+    const int H = (int)slot[0].size(), W = (int)slot[1].size();
+    const long lda = (long)V->opy.n * (V->opy.p + 2);
+    std::vector<float> la((size_t)H * W);
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j)
+            la[(size_t)i * W + j] = (float)std::log(std::max(V->a_host[(size_t)gidx[0][i] * lda + gidx[1][j]], 1e-300));
+    auto up = [](const void* h, size_t bytes, void** d) -> bool {
+        return hipMalloc(d, bytes) == hipSuccess && hipMemcpy(*d, h, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    const size_t hw = (size_t)H * W;
+    if (!up(slot[0].data(), H * sizeof(int), (void**)&V->sx) || !up(slot[1].data(), W * sizeof(int), (void**)&V->sy) ||
+        !up(la.data(), hw * sizeof(float), (void**)&V->loga) || !up(wts[0].data(), H * sizeof(float), (void**)&V->wx) ||
+        !up(wts[1].data(), W * sizeof(float), (void**)&V->wy) || dmalloc(&V->img, 3 * hw) != hipSuccess ||
+        dmalloc(&V->img_out, hw) != hipSuccess || dmalloc(&V->img_zn, hw) != hipSuccess ||
+        dmalloc(&V->img_t, hw) != hipSuccess || dmalloc(&V->img_w, hw) != hipSuccess)
+        return HPADI_ENOMEM;
+    V->H = H;
+    V->W = W;
+    return HPADI_OK;
+}
+
+}  // namespace hpadi_host
+

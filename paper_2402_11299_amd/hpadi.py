@@ -19,6 +19,7 @@ HPADI_FP64, HPADI_MIXED = 0, 1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_float_p = ctypes.POINTER(ctypes.c_float)
 
 
 class hpadi_stats(ctypes.Structure):
@@ -36,7 +37,7 @@ class hpadi_options(ctypes.Structure):
 
 class hpadi_krylov_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("precond_calls", ctypes.c_int),
-                ("reserved0", ctypes.c_int), ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("corrections", ctypes.c_int), ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
                 ("t_ms", ctypes.c_double), ("reserved", ctypes.c_double * 3)]
 
 
@@ -70,9 +71,27 @@ SIGNATURES = {
     "hpadi_varcoef_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                            ctypes.c_int]),
     "hpadi_varcoef_destroy": (None, [ctypes.c_void_p]),
-    "hpadi_fcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+    "hpadi_net_num_params": (ctypes.c_int, []),
+    "hpadi_net_create": (ctypes.c_int, [_c_float_p, ctypes.c_ulonglong, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_net_get_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
+    "hpadi_net_set_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
+    "hpadi_net_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p]),
+    "hpadi_net_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_double), _c_float_p]),
+    "hpadi_net_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_ulonglong, _c_float_p]),
+    "hpadi_net_pairs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                       _c_double_p, ctypes.c_int, ctypes.POINTER(hpadi_krylov_stats)]),
+                                       ctypes.c_int, ctypes.c_ulonglong, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _c_int_p]),
+    "hpadi_net_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_fcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.POINTER(hpadi_krylov_stats)]),
     "hpadi_plan_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hpadi_plan_timing_read": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, _c_int_p]),
     "hpadi_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -262,13 +281,13 @@ def hpadi_varcoef_destroy(vc):
     lib().hpadi_varcoef_destroy(vc)
 
 
-def hpadi_fcg_solve(vc, precond, b, x, tol, maxit, truncation, hist_len=0, raise_on_noconv=True):
+def hpadi_fcg_solve(vc, precond, b, x, tol, maxit, truncation, hist_len=0, raise_on_noconv=True, net=None):
     import numpy as np
     bp, ldb = _tptr(b)
     xp, ldx = _tptr(x)
     hist = np.zeros(max(hist_len, 1))
     st = hpadi_krylov_stats()
-    rc = lib().hpadi_fcg_solve(vc, precond, bp, ldb, xp, ldx, float(tol), int(maxit), int(truncation),
+    rc = lib().hpadi_fcg_solve(vc, precond, net, bp, ldb, xp, ldx, float(tol), int(maxit), int(truncation),
                                _dptr(hist) if hist_len > 0 else None, int(hist_len), ctypes.byref(st))
     if rc != HPADI_OK and (raise_on_noconv or rc != HPADI_ENOCONV):
         raise HpadiError(rc, "hpadi_fcg_solve")
@@ -388,18 +407,113 @@ class VarCoef:
         return Y
 
     def solve(self, b, precond: "Plan" = None, tol=1e-10, maxit=500, truncation=1, hist_len=0,
-              raise_on_noconv=True):
+              raise_on_noconv=True, net: "Net" = None):
         import torch
         if tuple(b.shape) != (self.x.N, self.y.N):
             raise ValueError(f"b must be {self.x.N} x {self.y.N}")
         x = torch.empty_like(b)
         st, hist = hpadi_fcg_solve(self.handle, precond.handle if precond is not None else None, b, x, tol,
-                                   maxit, truncation, hist_len, raise_on_noconv)
+                                   maxit, truncation, hist_len, raise_on_noconv,
+                                   net.handle if net is not None else None)
         return x, st, hist
+
+    def pairs(self, precond: "Plan", b, xstar, crop, crops_per_iter, cap, tol=1e-10, max_iters=500, seed=0):
+        """Training crops from the preconditioned CG iterates (see hpadi_net_pairs)."""
+        import torch
+        dev = b.device
+        X = torch.empty((cap, crop, crop, 3), dtype=torch.float32, device=dev)
+        ZN = torch.empty((cap, crop, crop), dtype=torch.float32, device=dev)
+        T = torch.empty_like(ZN)
+        W = torch.empty_like(ZN)
+        bp, ldb = _tptr(b)
+        xp, ldx = _tptr(xstar)
+        cnt = ctypes.c_int()
+        check(lib().hpadi_net_pairs(self.handle, precond.handle, bp, ldb, xp, ldx, float(tol), int(max_iters),
+                                    int(crop), int(crops_per_iter), ctypes.c_ulonglong(seed),
+                                    ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(ZN.data_ptr()),
+                                    ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(W.data_ptr()), int(cap),
+                                    ctypes.byref(cnt)), "hpadi_net_pairs")
+        k = cnt.value
+        return X[:k], ZN[:k], T[:k], W[:k]
 
     def close(self):
         if getattr(self, "handle", None) is not None:
             hpadi_varcoef_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _fptr_dev(t):
+    import torch
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA float32 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Net:
+    """Learned correction network (BF16 matrix-core kernels, FP32 parameters)."""
+
+    def __init__(self, params=None, seed=0, stream=None):
+        import numpy as np
+        h = ctypes.c_void_p()
+        self.nparams = lib().hpadi_net_num_params()
+        if params is not None:
+            arr = np.ascontiguousarray(params, dtype=np.float32)
+            if arr.size != self.nparams:
+                raise ValueError(f"expected {self.nparams} parameters")
+            pp = arr.ctypes.data_as(_c_float_p)
+        else:
+            pp = None
+        check(lib().hpadi_net_create(pp, ctypes.c_ulonglong(seed), _stream_handle(stream), ctypes.byref(h)),
+              "hpadi_net_create")
+        self.handle = h
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.nparams, dtype=np.float32)
+        check(lib().hpadi_net_get_params(self.handle, out.ctypes.data_as(_c_float_p)), "hpadi_net_get_params")
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32)
+        check(lib().hpadi_net_set_params(self.handle, arr.ctypes.data_as(_c_float_p)), "hpadi_net_set_params")
+
+    def forward(self, x):
+        import torch
+        B, H, W, C = x.shape
+        if C != 3:
+            raise ValueError("x must be B x H x W x 3")
+        out = torch.empty((B, H, W), dtype=torch.float32, device=x.device)
+        check(lib().hpadi_net_forward(self.handle, _fptr_dev(x), B, H, W, _fptr_dev(out)), "hpadi_net_forward")
+        return out
+
+    def loss_grad(self, x, zn, t, w):
+        import numpy as np
+        B, H, W, _ = x.shape
+        loss = ctypes.c_double()
+        g = np.zeros(self.nparams, dtype=np.float32)
+        check(lib().hpadi_net_loss_grad(self.handle, _fptr_dev(x), _fptr_dev(zn), _fptr_dev(t), _fptr_dev(w), B, H,
+                                        W, ctypes.byref(loss), g.ctypes.data_as(_c_float_p)), "hpadi_net_loss_grad")
+        return loss.value, g
+
+    def train(self, X, ZN, T, W, batch, steps, lr, seed=0):
+        import numpy as np
+        n, c = X.shape[0], X.shape[1]
+        hist = np.zeros(max(steps, 1), dtype=np.float32)
+        check(lib().hpadi_net_train(self.handle, _fptr_dev(X), _fptr_dev(ZN), _fptr_dev(T), _fptr_dev(W), n, c,
+                                    int(batch), int(steps), float(lr), ctypes.c_ulonglong(seed),
+                                    hist.ctypes.data_as(_c_float_p)), "hpadi_net_train")
+        return hist[:steps]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib().hpadi_net_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
