@@ -209,10 +209,12 @@ typedef struct {
  * (n_x p_x + 1) x (n_y p_y + 1) pixels.  Channels 3 -> 32 -> 32 -> 32 -> 1, 3x3
  * convolutions with zero padding, tanh-form GELU after the hidden layers; BF16
  * activations and weights on the matrix cores with FP32 accumulation, FP32
- * master parameters.  Inside the Krylov loop the preconditioned residual is
- * corrected as z <- z + s_z NN([z/s_z, r/s_r, log a]) (s: root-mean-square
- * values); a correction that is not finite or makes z.r <= 0 is dropped and
- * the plain z is used. */
+ * master parameters.  Inside the Krylov loop the preconditioned residual z is
+ * corrected by c = s_z NN([z/s_z, r/s_r, log a]) (s: root-mean-square values):
+ * z <- z + (beta/alpha) c with alpha z + beta c the energy-optimal combination
+ * (it minimises ||v - e||_A over span{z, c} for the error e of the iterate, which
+ * needs A z and A c: two extra operator applications per iteration); a
+ * degenerate or non-finite combination falls back to the plain z. */
 typedef struct hpadi_net_s* hpadi_net;
 
 /* Number of FP32 parameters: W0[3][3][3][32] b0[32] W1[3][3][32][32] b1[32]
@@ -241,7 +243,8 @@ int hpadi_net_train(hpadi_net net, const float* X_dev, const float* ZN_dev, cons
 /* Training pairs from the method: plain preconditioned CG (truncation 0) on
  * A_a x = b from x = 0; after the preconditioner of iteration k the images
  * [z/s_z, r/s_r, log a], zn = z/s_z, t = (xstar - x_k)/s_z and the slot weights
- * w (diagonal of M_x times diagonal of M_y) are formed and crops_per_iter
+ * w = a (diag K_x diag M_y + diag M_x diag K_y), the diagonal of the energy form,
+ * are formed and crops_per_iter
  * random c x c crops of them are appended to X (3 ch), ZN, T, Wt (FP32 device,
  * capacity cap crops).  xstar: the converged solution (device, ldxs).  Stops
  * after max_iters iterations, at convergence (tol) or when cap crops are

@@ -138,6 +138,7 @@ int ensure_work(hpadi_varcoef_s* V, int m) {
     const size_t n = (size_t)V->Nx * V->Ny;
     if (!V->r) {
         if (dmalloc(&V->r, n) != hipSuccess || dmalloc(&V->z, n) != hipSuccess || dmalloc(&V->zs, n) != hipSuccess ||
+            dmalloc(&V->Az, n) != hipSuccess || dmalloc(&V->Ac, n) != hipSuccess ||
             dmalloc(&V->part, 4 * (size_t)hpadi::dot_parts()) != hipSuccess || dmalloc(&V->dots, 8) != hipSuccess)
             return HPADI_ENOMEM;
         if (hipHostMalloc((void**)&V->dots_host, 8 * sizeof(double)) != hipSuccess) return HPADI_ENOMEM;
@@ -415,7 +416,7 @@ int ensure_slots(hpadi_varcoef_s* V) {
         gauss_legendre(q, t, w);
         slot[a].assign(S, -1);
         gidx[a].assign(S, 0);
-        wts[a].assign(S, 0.0f);
+        wts[a].assign(2 * S, 0.0f);  // [mass diagonal | stiffness diagonal] of the slot functions
         for (int s = 0; s < S; ++s) {
             const int e = std::min(s / o.p, o.n - 1);
             const int j = s - e * o.p;  // 0 = left vertex, p = right vertex (last slot), else bubble j-1
@@ -426,12 +427,14 @@ int ensure_slots(hpadi_varcoef_s* V) {
                     slot[a][s] = o.hat_of_vertex(v);
                     const double dl = v > 0 ? o.delta[v - 1] : 0.0, dr = v < o.n ? o.delta[v] : 0.0;
                     wts[a][s] = (float)((dl + dr) / 3.0);
+                    wts[a][S + s] = (float)((v > 0 ? 1.0 / dl : 0.0) + (v < o.n ? 1.0 / dr : 0.0));
                 }
                 xi = j == 0 ? -1.0 : 1.0;
             } else {
                 const int m = j - 1;
                 slot[a][s] = o.bubble(m, e);
                 wts[a][s] = (float)(2.0 * o.delta[e] / ((2.0 * m + 1) * (2.0 * m + 3) * (2.0 * m + 5)));
+                wts[a][S + s] = (float)(4.0 / ((2.0 * m + 3) * o.delta[e]));
                 xi = -1.0 + 2.0 * j / o.p;
             }
             int best = 0;
@@ -451,8 +454,8 @@ int ensure_slots(hpadi_varcoef_s* V) {
     };
     const size_t hw = (size_t)H * W;
     if (!up(slot[0].data(), H * sizeof(int), (void**)&V->sx) || !up(slot[1].data(), W * sizeof(int), (void**)&V->sy) ||
-        !up(la.data(), hw * sizeof(float), (void**)&V->loga) || !up(wts[0].data(), H * sizeof(float), (void**)&V->wx) ||
-        !up(wts[1].data(), W * sizeof(float), (void**)&V->wy) || dmalloc(&V->img, 3 * hw) != hipSuccess ||
+        !up(la.data(), hw * sizeof(float), (void**)&V->loga) || !up(wts[0].data(), 2 * H * sizeof(float), (void**)&V->wx) ||
+        !up(wts[1].data(), 2 * W * sizeof(float), (void**)&V->wy) || dmalloc(&V->img, 3 * hw) != hipSuccess ||
         dmalloc(&V->img_out, hw) != hipSuccess || dmalloc(&V->img_zn, hw) != hipSuccess ||
         dmalloc(&V->img_t, hw) != hipSuccess || dmalloc(&V->img_w, hw) != hipSuccess)
         return HPADI_ENOMEM;

@@ -20,7 +20,9 @@ struct hpadi_varcoef_s {
     // Krylov work (allocated on first use): r, z, the directions d_i and q_i = A d_i
     double* r = nullptr;
     double* z = nullptr;
-    double* zs = nullptr;         // copy of z before a learned correction
+    double* zs = nullptr;         // learned correction c of z
+    double* Az = nullptr;         // A z and A c for the energy-optimal combination
+    double* Ac = nullptr;
     std::vector<double*> d, q;
     double* part = nullptr;
     double* dots = nullptr;
@@ -48,6 +50,8 @@ struct hpadi_varcoef_s {
         (void)hipFree(r);
         (void)hipFree(z);
         (void)hipFree(zs);
+        (void)hipFree(Az);
+        (void)hipFree(Ac);
         (void)hipFree(part);
         (void)hipFree(dots);
         if (dots_host) (void)hipHostFree(dots_host);
@@ -72,9 +76,11 @@ int fcg_core(hpadi_varcoef_s* V, hpadi_plan precond, hpadi_net net, const double
              double tol, int maxit, int truncation, double* res_hist, int hist_len, hpadi_krylov_stats* stats,
              const KrylovObserver& observe);
 
-// z <- z + s_z NN([z/s_z, r/s_r, log a]) on the slot image (s = root-mean-square values);
-// *applied = false when the corrected z is rejected (not finite, or not a descent
-// direction: z.r <= 0), in which case z is left as it was.
+// Learned correction of the preconditioned residual: c = s_z NN([z/s_z, r/s_r, log a])
+// on the slot image (s = root-mean-square values), combined as z <- z + (beta/alpha) c
+// with (alpha, beta) minimising the energy error f(v) = v.Av - 2 v.r of alpha z + beta c
+// (the error equation is A e = r, and f(v) = ||v - e||_A^2 - e.r).  *applied = false
+// when the combination is degenerate or not finite; z is then left as it was.
 int net_correct(hpadi_net net, hpadi_varcoef_s* V, const double* r, double* z, bool* applied);
 
 }  // namespace hpadi_host

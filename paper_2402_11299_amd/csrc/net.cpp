@@ -380,47 +380,59 @@ int net_correct(hpadi_net N, hpadi_varcoef_s* V, const double* r, double* z, boo
     int rc = ensure_slots(V);
     if (rc != HPADI_OK) return rc;
     if ((rc = ensure_ws(N, (size_t)V->H * V->W, N->train_ws)) != HPADI_OK) return rc;
-    if (N->stream != st && hipStreamSynchronize(st) != hipSuccess) return HPADI_EHIP;
-    // norms: z.z, r.r, z.r before the correction
+    auto fetch = [&](int cnt) -> int {
+        if (hipMemcpyAsync(V->dots_host, V->dots, cnt * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return HPADI_EHIP;
+        return HPADI_OK;
+    };
     hpadi::MultiB mb{};
-    mb.nb = 2;
-    mb.b[0] = z;
-    mb.b[1] = r;
-    if (hpadi::launch_multidot(z, mb, n, V->part, V->dots, st) != hipSuccess) return HPADI_EHIP;
     mb.nb = 1;
+    mb.b[0] = z;
+    if (hpadi::launch_multidot(z, mb, n, V->part, V->dots, st) != hipSuccess) return HPADI_EHIP;
     mb.b[0] = r;
-    if (hpadi::launch_multidot(r, mb, n, V->part, V->dots + 2, st) != hipSuccess ||
-        hipMemcpyAsync(V->dots_host, V->dots, 3 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return HPADI_EHIP;
-    const double zz = V->dots_host[0], rr = V->dots_host[2];
+    if (hpadi::launch_multidot(r, mb, n, V->part, V->dots + 1, st) != hipSuccess) return HPADI_EHIP;
+    if ((rc = fetch(2)) != HPADI_OK) return rc;
+    const double zz = V->dots_host[0], rr = V->dots_host[1];
     if (!(zz > 0.0) || !(rr > 0.0)) return HPADI_OK;
     const double sz = std::sqrt(zz / n), sr = std::sqrt(rr / n);
     hpadi::SlotMap mp{V->H, V->W, V->sx, V->sy, V->loga};
-    // keep the plain z in case the correction is rejected
-    double* zsave = V->zs;
-    if (hipMemcpyAsync(zsave, z, n * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
-        hpadi::launch_pack_image(mp, z, r, V->Ny, 1.0 / sz, 1.0 / sr, V->img, st) != hipSuccess)
-        return HPADI_EHIP;
+    double* c = V->zs;
+    if (hpadi::launch_pack_image(mp, z, r, V->Ny, 1.0 / sz, 1.0 / sr, V->img, st) != hipSuccess) return HPADI_EHIP;
     if (N->stream != st && hipStreamSynchronize(st) != hipSuccess) return HPADI_EHIP;
     if ((rc = forward(N, V->img, ImgShape{1, V->H, V->W}, V->img_out, false)) != HPADI_OK) return rc;
     if (N->stream != st && hipStreamSynchronize(N->stream) != hipSuccess) return HPADI_EHIP;
-    if (hpadi::launch_unpack_add(mp, V->img_out, sz, z, V->Ny, st) != hipSuccess) return HPADI_EHIP;
-    // accept only a finite descent direction
-    mb.nb = 2;
-    mb.b[0] = z;
-    mb.b[1] = r;
-    if (hpadi::launch_multidot(z, mb, n, V->part, V->dots, st) != hipSuccess ||
-        hipMemcpyAsync(V->dots_host, V->dots, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
+    if (hipMemsetAsync(c, 0, n * sizeof(double), st) != hipSuccess ||
+        hpadi::launch_unpack_add(mp, V->img_out, sz, c, V->Ny, st) != hipSuccess ||
+        hpadi::launch_vc_apply(V->dev, z, V->Ny, V->Az, V->Ny, st) != hipSuccess ||
+        hpadi::launch_vc_apply(V->dev, c, V->Ny, V->Ac, V->Ny, st) != hipSuccess)
         return HPADI_EHIP;
-    const double zz2 = V->dots_host[0], zr2 = V->dots_host[1];
-    if (std::isfinite(zz2) && std::isfinite(zr2) && zr2 > 0.0) {
-        *applied = true;
-        return HPADI_OK;
-    }
-    return hipMemcpyAsync(z, zsave, n * sizeof(double), hipMemcpyDeviceToDevice, st) == hipSuccess ? HPADI_OK
-                                                                                                    : HPADI_EHIP;
+    // z.Az, z.Ac, z.r, c.Ac, c.r
+    mb.nb = 3;
+    mb.b[0] = V->Az;
+    mb.b[1] = V->Ac;
+    mb.b[2] = r;
+    if (hpadi::launch_multidot(z, mb, n, V->part, V->dots, st) != hipSuccess) return HPADI_EHIP;
+    mb.nb = 2;
+    mb.b[0] = V->Ac;
+    mb.b[1] = r;
+    if (hpadi::launch_multidot(c, mb, n, V->part, V->dots + 3, st) != hipSuccess) return HPADI_EHIP;
+    if ((rc = fetch(5)) != HPADI_OK) return rc;
+    const double zAz = V->dots_host[0], zAc = V->dots_host[1], zr = V->dots_host[2];
+    const double cAc = V->dots_host[3], cr = V->dots_host[4];
+    // minimise [a b] G [a b]^T - 2 [a b] g with G = [[zAz, zAc], [zAc, cAc]], g = [zr, cr]
+    const double det = zAz * cAc - zAc * zAc;
+    if (!(zAz > 0.0) || !(cAc > 0.0) || !(det > 1e-12 * zAz * cAc) || !std::isfinite(det)) return HPADI_OK;
+    const double alpha = (cAc * zr - zAc * cr) / det, beta = (zAz * cr - zAc * zr) / det;
+    if (!(alpha > 0.0) || !std::isfinite(beta)) return HPADI_OK;
+    hpadi::MultiB xs{};
+    hpadi::Coefs cc{};
+    xs.nb = 1;
+    xs.b[0] = c;
+    cc.c[0] = beta / alpha;
+    if (hpadi::launch_axpys(z, xs, cc, n, st) != hipSuccess) return HPADI_EHIP;
+    *applied = true;
+    return HPADI_OK;
 }
 
 }  // namespace hpadi_host

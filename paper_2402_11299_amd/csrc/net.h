@@ -73,7 +73,9 @@ hipError_t launch_unpack_add(const SlotMap& m, const float* o, double sz, double
 // training pairs: crops (y0, x0) of size c from full images (H x W): inputs (3 ch), zn, t, w
 hipError_t launch_crop(const float* x, const float* zn, const float* t, const float* w, int H, int W, int c,
                        const int* pos /* [n][2] */, int n, float* cx, float* czn, float* ct, float* cw, hipStream_t st);
-// target and weight images: t = (xs - x) / s_z at the slots, zn = z / s_z, w = w_x w_y
+// target and weight images: t = (xs - x) / s_z at the slots, zn = z / s_z and the loss
+// weight w = a (k_x m_y + m_x k_y), the diagonal of the energy form at the slot
+// (wx = [m_x | k_x], wy = [m_y | k_y]: mass and stiffness diagonals of the slot functions)
 hipError_t launch_target_image(const SlotMap& m, const double* xs, const double* x, const double* z, long ld,
                                double inv_sz, const float* wx, const float* wy, float* zn, float* t, float* w,
                                hipStream_t st);

@@ -403,7 +403,8 @@ __global__ void target_image_kernel(SlotMap mp, const double* xs, const double* 
     const long q = (long)gi * ld + gj;
     zn[p] = ok ? (float)(z[q] * isz) : 0.0f;
     t[p] = ok ? (float)((xs[q] - x[q]) * isz) : 0.0f;
-    w[p] = ok ? wx[i] * wy[j] : 0.0f;
+    // diagonal of the energy form a (K (x) M + M (x) K) at the slot
+    w[p] = ok ? expf(mp.loga[p]) * (wx[mp.H + i] * wy[j] + wx[i] * wy[mp.W + j]) : 0.0f;
 }
 
 __global__ void crop_kernel(const float* x, const float* zn, const float* t, const float* w, int H, int W, int c,
