@@ -166,6 +166,32 @@ int hpadi_apply(hpadi_plan plan, const double* U_dev, int ldu, double* Y_dev, in
 
 void hpadi_plan_destroy(hpadi_plan plan);
 
+/* ---- Batches of independent solves ------------------------------------- */
+
+/* count independent problems A_Y^x U M^y + M^x U A_Y^y = G (operators xs[i],
+ * ys[i], omega2[i]; any sizes, degrees and boundary conditions) solved to the
+ * relative error tol, replayed as one HIP graph.  Each instance has a MIXED plan
+ * and a fixed schedule of one round with FP32 storage and one FP64 round; the
+ * instances are spread over nstreams (0 = 8) concurrent capture streams,
+ * largest first onto the least loaded stream (work estimate N_x N_y log(N_x N_y)).
+ * autotune != 0: for every distinct (n_x, p_x, n_y, p_y, bc) the lines per
+ * workgroup (4 or 8) is chosen by timing both on the instance (this runs solves
+ * and overwrites U[i]).  G[i], U[i]: FP64 device arrays N_x x N_y (ld ldg[i],
+ * ldu[i]) bound to the graph: later solves read and write these same arrays.
+ * hip_stream: the stream the graph is launched on (a hipStream_t or NULL). */
+typedef struct hpadi_batch_s* hpadi_batch;
+int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, const double* omega2, double tol,
+                       const double* const* G, const int* ldg, double* const* U, const int* ldu, int autotune,
+                       int nstreams, void* hip_stream, hpadi_batch* out);
+/* Launch the graph and wait for it; then, per instance, the ADI lemma bound of
+ * its FP64 round (as in hpadi_solve); instances above tol get further FP64
+ * rounds outside the graph (*n_extra counts them; may be NULL).  stats: host
+ * array of count entries or NULL.  ENOCONV if an instance stays above tol. */
+int hpadi_batch_solve(hpadi_batch b, hpadi_stats* stats, int* n_extra);
+/* Tuned lines per workgroup, J and capture stream of instance i (any pointer may be NULL). */
+int hpadi_batch_info(hpadi_batch b, int i, int* lines_per_block, int* J, int* stream_index);
+void hpadi_batch_destroy(hpadi_batch b);
+
 /* ---- Variable coefficient and ADI-preconditioned CG (Sec. 7) ----------- */
 
 /* -div(a grad u) = f with the same bases and boundary conditions as the plans:

@@ -668,7 +668,81 @@ int ensure_fp64_work(hpadi_plan_s* P) {
     return HPADI_OK;
 }
 
+// r = G - A U in FP64 into P->R64 (norms accumulated into P->acc[2..3]).
+int residual_into_r64(hpadi_plan_s* P, const double* G, long ldg, const double* U, long ldu) {
+    hipStream_t s = P->stream;
+    int rc = row_products(P, U, ldu);
+    if (rc != HPADI_OK) return rc;
+    if (hpadi::launch_zero_f64(P->acc + 2, 2, 1, 2, s) != hipSuccess) return HPADI_EHIP;
+    hpadi::Residual r{};
+    r.G = G;
+    r.g_ld = ldg;
+    r.T1 = P->T1;
+    r.T2 = P->T2;
+    r.t_ld = P->ldw;
+    r.r64 = P->R64;
+    r.r64_ld = P->ldw;
+    r.ax_k = 1.0;
+    r.ax_t = P->omega2 / 2.0;
+    r.alpha = 1.0;
+    r.beta = -1.0;
+    r.ncols = P->dy.op.N;
+    r.norm_acc = P->acc + 2;
+    r.wcol = P->dy.dev.mdiag;
+    return hpadi::launch_residual(P->dx.dev, r, s) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+}
+
+// A refinement schedule with a fixed number of rounds (nfp32 rounds with FP32 storage,
+// then nfp64 FP64 rounds) and no host synchronisation or memset node, so that it can be
+// captured into a graph.  P->acc[0..1] hold the norms of the last round's correction
+// and of U for the error bound.  Work arrays must already exist.
+int enqueue_fixed_solve(hpadi_plan_s* P, const double* G, long ldg, double* U, long ldu, int nfp32, int nfp64) {
+    hipStream_t s = P->stream;
+    if (hpadi::launch_zero_f64(U, ldu, P->dx.op.N, P->dy.op.N, s) != hipSuccess) return HPADI_EHIP;
+    const int rounds = nfp32 + nfp64;
+    for (int k = 1; k <= rounds; ++k) {
+        const int ts = k <= nfp32 ? 4 : 8;
+        int rc;
+        if (k > 1 && (rc = residual_into_r64(P, G, ldg, U, ldu)) != HPADI_OK) return rc;
+        if (hpadi::launch_zero_f64(P->acc, 2, 1, 2, s) != hipSuccess) return HPADI_EHIP;
+        if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
+        if ((rc = run_adi(P, ts, U, ldu, true)) != HPADI_OK) return rc;
+    }
+    return HPADI_OK;
+}
+
 }  // namespace
+
+// ===========================================================================
+// Batched solves: independent plans replayed as one graph.
+// ===========================================================================
+struct hpadi_batch_s {
+    int count = 0;
+    std::vector<hpadi_plan> plans;
+    std::vector<const double*> G;
+    std::vector<double*> U;
+    std::vector<int> ldg, ldu, lw, stream_of;
+    std::vector<hipStream_t> side;
+    hipStream_t origin = nullptr;
+    bool own_origin = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double tol = 0.0;
+    const double** acc_ptrs = nullptr;   // device array of the plans' accumulators
+    double* acc_all = nullptr;           // device [count][2]
+    double* acc_host = nullptr;          // pinned copy
+    ~hpadi_batch_s() {
+        if (origin) (void)hipStreamSynchronize(origin);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hpadi_plan p : plans) hpadi_plan_destroy(p);
+        for (hipStream_t st : side) (void)hipStreamDestroy(st);
+        if (own_origin) (void)hipStreamDestroy(origin);
+        (void)hipFree(acc_ptrs);
+        (void)hipFree(acc_all);
+        if (acc_host) (void)hipHostFree(acc_host);
+    }
+};
 
 // ===========================================================================
 // C ABI.
@@ -1065,6 +1139,223 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
     if (stats) *stats = st;
     return rc;
 }
+
+int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, const double* omega2, double tol,
+                       const double* const* G, const int* ldg, double* const* U, const int* ldu, int autotune,
+                       int nstreams, void* hip_stream, hpadi_batch* out) {
+    if (count < 1 || !xs || !ys || !omega2 || !G || !ldg || !U || !ldu || !out || !(tol > 0.0)) return HPADI_EINVAL;
+    *out = nullptr;
+    hpadi_batch_s* B = new (std::nothrow) hpadi_batch_s();
+    if (!B) return HPADI_ENOMEM;
+    B->count = count;
+    B->tol = tol;
+    B->origin = (hipStream_t)hip_stream;
+    if (!B->origin) {
+        // the legacy default stream cannot be captured: launch the graph on a stream of our own
+        if (hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking) != hipSuccess) {
+            delete B;
+            return HPADI_EHIP;
+        }
+        B->own_origin = true;
+    }
+    const int S = std::max(1, std::min(nstreams > 0 ? nstreams : 8, count));
+    for (int i = 0; i < S; ++i) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            delete B;
+            return HPADI_EHIP;
+        }
+        B->side.push_back(st);
+    }
+    // longest work first onto the least loaded stream (work ~ J N_x N_y, J ~ log of the
+    // spectral ratio: use N_x N_y log(N_x N_y) as the estimate)
+    std::vector<int> order(count);
+    std::vector<double> work(count);
+    for (int i = 0; i < count; ++i) {
+        if (!xs[i] || !ys[i]) {
+            delete B;
+            return HPADI_EINVAL;
+        }
+        const double d = (double)xs[i]->N * ys[i]->N;
+        work[i] = d * std::log(2.0 + d);
+        order[i] = i;
+    }
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<double> load(S, 0.0);
+    B->stream_of.assign(count, 0);
+    for (int i : order) {
+        const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        B->stream_of[i] = st;
+        load[st] += work[i];
+    }
+    // autotuner: lines per workgroup (4 or 8) per distinct (n_x, p_x, n_y, p_y, bc), by timing
+    // one fixed-schedule solve of each candidate on the instance's own data
+    std::vector<std::pair<std::vector<int>, int>> tuned;
+    B->plans.assign(count, nullptr);
+    B->lw.assign(count, 8);
+    B->G.assign(G, G + count);
+    B->U.assign(U, U + count);
+    B->ldg.assign(ldg, ldg + count);
+    B->ldu.assign(ldu, ldu + count);
+    auto make_plan = [&](int i, int lw, hpadi_plan* pl) -> int {
+        hpadi_options o{};
+        o.lines_per_block = lw;
+        int rc = hpadi_plan_create_ex(xs[i], ys[i], omega2[i], tol, HPADI_MIXED, nullptr, B->side[B->stream_of[i]],
+                                      &o, pl);
+        if (rc != HPADI_OK) return rc;
+        hpadi_plan_s* P = *pl;
+        if ((rc = ensure_fp64_work(P)) != HPADI_OK) return rc;
+        if (!P->R64 && dmalloc(&P->R64, (size_t)P->dx.op.N * P->ldw) != hipSuccess) return HPADI_ENOMEM;
+        return HPADI_OK;
+    };
+    for (int i = 0; i < count; ++i) {
+        const std::vector<int> key = {xs[i]->n, xs[i]->p, ys[i]->n, ys[i]->p, xs[i]->bc};
+        int lw = 8;
+        bool found = false;
+        for (auto& kv : tuned)
+            if (kv.first == key) {
+                lw = kv.second;
+                found = true;
+            }
+        int rc = HPADI_OK;
+        if (!found && autotune) {
+            double best = 1e300;
+            for (int cand : {8, 4}) {
+                hpadi_plan pl = nullptr;
+                if ((rc = make_plan(i, cand, &pl)) != HPADI_OK) {
+                    hpadi_plan_destroy(pl);
+                    delete B;
+                    return rc;
+                }
+                hipStream_t st = pl->stream;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                float ms = 0.0f;
+                bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+                ok = ok && enqueue_fixed_solve(pl, G[i], ldg[i], U[i], ldu[i], 1, 1) == HPADI_OK;  // warm-up
+                ok = ok && hipEventRecord(e0, st) == hipSuccess &&
+                     enqueue_fixed_solve(pl, G[i], ldg[i], U[i], ldu[i], 1, 1) == HPADI_OK &&
+                     hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+                if (!ok) {
+                    hpadi_plan_destroy(pl);
+                    delete B;
+                    return HPADI_EHIP;
+                }
+                if (ms < best) {
+                    best = ms;
+                    lw = cand;
+                    if (B->plans[i]) hpadi_plan_destroy(B->plans[i]);
+                    B->plans[i] = pl;
+                } else {
+                    hpadi_plan_destroy(pl);
+                }
+            }
+            tuned.push_back({key, lw});
+        }
+        B->lw[i] = lw;
+        if (!B->plans[i] && (rc = make_plan(i, lw, &B->plans[i])) != HPADI_OK) {
+            delete B;
+            return rc;
+        }
+    }
+    // device table of accumulator pointers and their gathered copy
+    std::vector<const double*> accs(count);
+    for (int i = 0; i < count; ++i) accs[i] = B->plans[i]->acc;
+    if (dmalloc(&B->acc_ptrs, (size_t)count) != hipSuccess || dmalloc(&B->acc_all, 2 * (size_t)count) != hipSuccess ||
+        hipHostMalloc((void**)&B->acc_host, 2 * (size_t)count * sizeof(double)) != hipSuccess ||
+        hipMemcpy(B->acc_ptrs, accs.data(), count * sizeof(double*), hipMemcpyHostToDevice) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        delete B;
+        return HPADI_ENOMEM;
+    }
+    // capture: origin -> every side stream -> instances in load order -> join -> gather accumulators
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins(S, nullptr);
+    bool ok = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < S; ++k) ok = hipEventCreateWithFlags(&joins[k], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed) == hipSuccess;
+    ok = ok && hipEventRecord(fork, B->origin) == hipSuccess;
+    for (int k = 0; ok && k < S; ++k) ok = hipStreamWaitEvent(B->side[k], fork, 0) == hipSuccess;
+    for (int i : order) {
+        if (!ok) break;
+        ok = enqueue_fixed_solve(B->plans[i], G[i], ldg[i], U[i], ldu[i], 1, 1) == HPADI_OK;
+    }
+    for (int k = 0; ok && k < S; ++k)
+        ok = hipEventRecord(joins[k], B->side[k]) == hipSuccess && hipStreamWaitEvent(B->origin, joins[k], 0) == hipSuccess;
+    ok = ok && hpadi::launch_gather_acc(B->acc_ptrs, count, B->acc_all, B->origin) == hipSuccess;
+    const bool ended = hipStreamEndCapture(B->origin, &B->graph) == hipSuccess;
+    ok = ok && ended && hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipEvent_t e : joins)
+        if (e) (void)hipEventDestroy(e);
+    if (!ok) {
+        delete B;
+        return HPADI_EHIP;
+    }
+    *out = B;
+    return HPADI_OK;
+}
+
+int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
+    if (!B) return HPADI_EINVAL;
+    if (hipGraphLaunch(B->exec, B->origin) != hipSuccess ||
+        hipMemcpyAsync(B->acc_host, B->acc_all, 2 * (size_t)B->count * sizeof(double), hipMemcpyDeviceToHost,
+                       B->origin) != hipSuccess ||
+        hipStreamSynchronize(B->origin) != hipSuccess)
+        return HPADI_EHIP;
+    // lemma bound of the FP64 round; instances above the tolerance get further FP64 rounds
+    constexpr double kNormSafety = 2.0;
+    int extra = 0, status = HPADI_OK;
+    for (int i = 0; i < B->count; ++i) {
+        hpadi_plan_s* P = B->plans[i];
+        const double eps = P->adi_eps;
+        double nd = std::sqrt(std::max(B->acc_host[2 * i], 0.0)), nu = std::sqrt(std::max(B->acc_host[2 * i + 1], 0.0));
+        double est = nu > 0 ? kNormSafety * eps / (1.0 - eps) * nd / nu : 0.0;
+        int rounds = 2;
+        while (est > B->tol && rounds < P->opt.max_rounds) {
+            int rc = residual_into_r64(P, B->G[i], B->ldg[i], B->U[i], B->ldu[i]);
+            if (rc == HPADI_OK && hpadi::launch_zero_f64(P->acc, 2, 1, 2, P->stream) != hipSuccess) rc = HPADI_EHIP;
+            if (rc == HPADI_OK) rc = transform_rhs(P, P->R64, P->ldw, 8);
+            if (rc == HPADI_OK) rc = run_adi(P, 8, B->U[i], B->ldu[i], true);
+            if (rc == HPADI_OK &&
+                (hipMemcpyAsync(P->acc_host, P->acc, 2 * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
+                 hipStreamSynchronize(P->stream) != hipSuccess))
+                rc = HPADI_EHIP;
+            if (rc != HPADI_OK) return rc;
+            nd = std::sqrt(std::max(P->acc_host[0], 0.0));
+            nu = std::sqrt(std::max(P->acc_host[1], 0.0));
+            est = nu > 0 ? kNormSafety * eps / (1.0 - eps) * nd / nu : 0.0;
+            ++rounds;
+            ++extra;
+        }
+        if (!(est <= B->tol)) status = HPADI_ENOCONV;
+        if (stats) {
+            hpadi_stats st{};
+            st.J = P->J;
+            st.rounds = rounds;
+            st.fp32_rounds = 1;
+            st.iters = rounds * P->J;
+            st.status = est <= B->tol ? HPADI_OK : HPADI_ENOCONV;
+            st.est_rel_err = est;
+            for (int k = 0; k < 4; ++k) st.interval[k] = P->interval[k];
+            stats[i] = st;
+        }
+    }
+    if (n_extra) *n_extra = extra;
+    return status;
+}
+
+int hpadi_batch_info(hpadi_batch B, int i, int* lines_per_block, int* J, int* stream_index) {
+    if (!B || i < 0 || i >= B->count) return HPADI_EINVAL;
+    if (lines_per_block) *lines_per_block = B->lw[i];
+    if (J) *J = B->plans[i]->J;
+    if (stream_index) *stream_index = B->stream_of[i];
+    return HPADI_OK;
+}
+
+void hpadi_batch_destroy(hpadi_batch B) { delete B; }
 
 int hpadi_plan_timing(hpadi_plan P, int enable) {
     if (!P) return HPADI_EINVAL;

@@ -71,6 +71,11 @@ struct hpadi_plan_s {
     size_t nrec = 0;
 };
 
+namespace hpadi {
+// out[2 i + k] = accs[i][k], k = 0, 1 (gathers the plans' norm accumulators of a batch)
+hipError_t launch_gather_acc(const double* const* accs, int count, double* out, hipStream_t s);
+}  // namespace hpadi
+
 namespace hpadi_host {
 
 template <typename T>

@@ -369,4 +369,18 @@ hipError_t launch_zero_f64(double* dst, long ld, int rows, int cols, hipStream_t
     return hipGetLastError();
 }
 
+namespace {
+__global__ void gather_acc_kernel(const double* const* accs, int count, double* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    out[2 * i] = accs[i][0];
+    out[2 * i + 1] = accs[i][1];
+}
+}  // namespace
+
+hipError_t launch_gather_acc(const double* const* accs, int count, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(gather_acc_kernel, dim3((count + 255) / 256), dim3(256), 0, s, accs, count, out);
+    return hipGetLastError();
+}
+
 }  // namespace hpadi

@@ -65,6 +65,14 @@ SIGNATURES = {
                                    ctypes.POINTER(hpadi_stats)]),
     "hpadi_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "hpadi_plan_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_void_p), _c_double_p, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_void_p), _c_int_p, ctypes.POINTER(ctypes.c_void_p),
+                                          _c_int_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_batch_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(hpadi_stats), _c_int_p]),
+    "hpadi_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_int_p, _c_int_p, _c_int_p]),
+    "hpadi_batch_destroy": (None, [ctypes.c_void_p]),
     "hpadi_varcoef_grid": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, ctypes.c_int]),
     "hpadi_varcoef_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
@@ -514,6 +522,63 @@ class Net:
     def close(self):
         if getattr(self, "handle", None) is not None:
             lib().hpadi_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent solves replayed as one graph (hpadi_batch_*).  problems: list of
+    (Op1D x, Op1D y, omega2); G, U: lists of FP64 CUDA tensors bound to the graph."""
+
+    def __init__(self, problems, tol, G, U, autotune=True, nstreams=0, stream=None):
+        n = len(problems)
+        if len(G) != n or len(U) != n:
+            raise ValueError("one G and one U per problem")
+        self.problems, self.G, self.U = problems, G, U
+        VP = ctypes.c_void_p * n
+        xs = VP(*[pr[0].handle.value if hasattr(pr[0].handle, "value") else pr[0].handle for pr in problems])
+        ys = VP(*[pr[1].handle.value if hasattr(pr[1].handle, "value") else pr[1].handle for pr in problems])
+        w2 = (ctypes.c_double * n)(*[float(pr[2]) for pr in problems])
+        gp, ldg, up, ldu = [], [], [], []
+        for g, u, pr in zip(G, U, problems):
+            if tuple(g.shape) != (pr[0].N, pr[1].N) or tuple(u.shape) != tuple(g.shape):
+                raise ValueError("G and U must be N_x x N_y")
+            a, la = _tptr(g)
+            b, lb = _tptr(u)
+            gp.append(a.value)
+            ldg.append(la)
+            up.append(b.value)
+            ldu.append(lb)
+        self._keep = (xs, ys, w2, VP(*gp), (ctypes.c_int * n)(*ldg), VP(*up), (ctypes.c_int * n)(*ldu))
+        h = ctypes.c_void_p()
+        check(lib().hpadi_batch_create(n, xs, ys, w2, float(tol), self._keep[3], self._keep[4], self._keep[5],
+                                       self._keep[6], int(bool(autotune)), int(nstreams), _stream_handle(stream),
+                                       ctypes.byref(h)), "hpadi_batch_create")
+        self.handle = h
+        self.count = n
+
+    def solve(self, raise_on_noconv=True):
+        st = (hpadi_stats * self.count)()
+        extra = ctypes.c_int()
+        rc = lib().hpadi_batch_solve(self.handle, st, ctypes.byref(extra))
+        if rc != HPADI_OK and (raise_on_noconv or rc != HPADI_ENOCONV):
+            raise HpadiError(rc, "hpadi_batch_solve")
+        return list(st), extra.value
+
+    def info(self, i):
+        lw, J, si = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().hpadi_batch_info(self.handle, int(i), ctypes.byref(lw), ctypes.byref(J), ctypes.byref(si)),
+              "hpadi_batch_info")
+        return lw.value, J.value, si.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            lib().hpadi_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
