@@ -79,10 +79,12 @@ typedef struct {
 typedef struct {
     double inner_tol;   /* mixed mode: tolerance of the shift family of every round (0 = 3e-6) */
     int max_rounds;     /* mixed mode: refinement round limit (0 = 8) */
-    int lines_per_block; /* half-sweep workgroup width, 4 or 8 lines (0 = 8) */
+    int lines_per_block; /* half-sweep workgroup width: 1, 4 or 8 lines (0 = 8); 1 needs n % 64 == 0 on
+                            that axis (else 8); 4 also selects 4-column panels in the internal layout */
     int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
     int fp32_rounds;    /* mixed mode: leading rounds with FP32 sweeps; later rounds are FP64 (0 = 1) */
-    int reserved[3];
+    int col_lines_per_block; /* column half-sweeps only: 1 or 8 lines (0 = as lines_per_block) */
+    int reserved[2];
 } hpadi_options;
 
 /* ---- 1D operators (Sec. 2, Sec. 3.1, App. A) -------------------------- */

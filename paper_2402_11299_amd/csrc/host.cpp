@@ -573,7 +573,7 @@ hpadi::SweepArgs sweep_args(const hpadi_plan_s* P, bool column, int j) {
     a.coef = coef ? coef + (size_t)j * D.op.p * 8 : nullptr;
     const double* ptab = column ? P->ptabx : P->ptaby;
     a.ptab = ptab ? ptab + (size_t)(j < P->J ? j : 0) * D.op.p * 16 : nullptr;
-    a.lpb = P->lint.panel;
+    a.lpb = column ? P->lpb_col : P->lpb_row;
     a.idx32 = P->nint < (size_t(1) << 31) ? 1 : 0;
     return a;
 }
@@ -968,8 +968,16 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     const int Nx = x->N, Ny = y->N;
     P->ldw = ((long)Ny + 63) / 64 * 64;
     hpadi::Layout& L = P->lint;
-    // 8-line workgroups unless 4 are asked for (measured faster in FP32 at n = p = 64)
+    // panel width of the internal layout: 4 when 4-line workgroups are asked for, else 8;
+    // lines per workgroup of the ADI half-sweeps: 1, 4 or 8 per direction
     const int pw = P->opt.lines_per_block == 4 ? 4 : 8;
+    auto lines = [&](int req, int n_line_axis) {
+        if (req == 1 && n_line_axis % 64 == 0) return 1;
+        return pw;
+    };
+    // a column pass runs along x (chains of the x basis), a row pass along y
+    P->lpb_col = lines(P->opt.col_lines_per_block > 0 ? P->opt.col_lines_per_block : P->opt.lines_per_block, x->n);
+    P->lpb_row = lines(P->opt.lines_per_block, y->n);
     L.panel = pw;
     L.nhr = x->nh;
     L.nhc = y->nh;

@@ -38,6 +38,7 @@ struct hpadi_plan_s {
     double interval[4] = {0, 0, 0, 0};
     int J = 0;
     double adi_eps = 0.0;         // tolerance the shift family was built for
+    int lpb_col = 8, lpb_row = 8; // lines per workgroup of the column / row half-sweeps
     std::vector<double> P, Q;
     hipStream_t stream = nullptr;
     bool shared = false;          // x and y use one factor family

@@ -77,8 +77,19 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
         FM.cpl[i] = Mf[fl.off_cpl + i];
     }
 
+    // One line per workgroup in a column pass: the 8 columns of a panel share every
+    // 32-byte sector, so their workgroups are placed on one XCD (workgroup b runs on
+    // XCD b mod 8) in consecutive dispatch slots, where they share that XCD's L2.
+    int blk = blockIdx.x;
+    if (LW == 1 && COL) {
+        const int full = (int)(gridDim.x / 64) * 64;
+        if (blk < full) {
+            const int xcd = blk % 8, slot = blk / 8;
+            blk = ((slot / 8) * 8 + xcd) * 8 + slot % 8;
+        }
+    }
     auto line_of = [&](int ll) -> int {
-        const int lint = blockIdx.x * LW + ll;
+        const int lint = blk * LW + ll;
         if (lint < a.nh_lines) return lint;
         if (lint < a.hpad_lines) return -1;
         return lint - (a.hpad_lines - a.nh_lines);
@@ -374,13 +385,22 @@ hipError_t launch_u(const DimDev& d, const SweepArgs& a, hipStream_t s) {
     const int threads = 64 * ((2 * d.n + CW - 1) / CW);
     if (threads > sweep_max_threads(CL) || d.nh > 65) return hipErrorInvalidValue;
     const int blocks = (a.hpad_lines + a.nlines - a.nh_lines + LW - 1) / LW;
+    // LDS: per line A, B (hats) and H1, H2 (chain heads), then the two hat factors
+    const int hs = d.nh + 1;
+    size_t words = (size_t)LW * (2 * hs + 4 * d.n) + 2 * (3 * hs + 4 * d.n);
+    if (MODE == SWEEP_FINAL && words < (size_t)threads * 2) words = (size_t)threads * 2;
     hipLaunchKernelGGL((sweep_uni_kernel<TIN, TOUT, CL, MODE, COL, LW>), dim3(blocks), dim3(threads),
-                       sweep_lds_bytes(d, threads, MODE), s, d, a);
+                       words * sizeof(double), s, d, a);
     return hipGetLastError();
 }
 
 template <typename TIN, typename TOUT, int CL, int MODE>
 hipError_t by_dir(const DimDev& d, const SweepArgs& a, bool col, hipStream_t s) {
+    // one line per workgroup for the ADI half-sweeps only (the transforms keep 8)
+    if constexpr (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE) {
+        if (a.lpb == 1)
+            return col ? launch_u<TIN, TOUT, CL, MODE, true, 1>(d, a, s) : launch_u<TIN, TOUT, CL, MODE, false, 1>(d, a, s);
+    }
     if (a.lpb == 4) return col ? launch_u<TIN, TOUT, CL, MODE, true, 4>(d, a, s) : launch_u<TIN, TOUT, CL, MODE, false, 4>(d, a, s);
     return col ? launch_u<TIN, TOUT, CL, MODE, true, 8>(d, a, s) : launch_u<TIN, TOUT, CL, MODE, false, 8>(d, a, s);
 }

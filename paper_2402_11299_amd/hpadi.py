@@ -32,7 +32,8 @@ class hpadi_stats(ctypes.Structure):
 class hpadi_options(ctypes.Structure):
     _fields_ = [("inner_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
                 ("lines_per_block", ctypes.c_int),
-                ("fixed_rounds", ctypes.c_int), ("fp32_rounds", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("fixed_rounds", ctypes.c_int), ("fp32_rounds", ctypes.c_int),
+                ("col_lines_per_block", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class hpadi_krylov_stats(ctypes.Structure):

@@ -52,3 +52,28 @@ def test_full_size_round_trip(hp, cfg, prec, draw):
     assert st.status == hp.HPADI_OK
     assert err <= cfg.tol
     plan.close()
+
+
+@pytest.mark.parametrize("lw,clw", [(1, 0), (8, 1), (1, 8), (4, 0)])
+def test_full_size_workgroup_widths(hp, lw, clw):
+    """The same round trip with one line per workgroup (column passes placed panel by
+    panel on one XCD) and the other widths of the half-sweeps."""
+    import torch
+    cfg = workloads.CFG_MIXED_4K_D
+    print(f"full-size round trip lines_per_block={lw} col={clw}", flush=True)
+    ox = obasis.assemble(obasis.make_basis(cfg.nx, cfg.px, cfg.ax, cfg.bx, cfg.bc))
+    oy = obasis.assemble(obasis.make_basis(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc))
+    U0 = workloads.decaying_coefficients(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.bc, seed=cfg.seed + 300)
+    G0 = oadi.apply_operator(ox, oy, cfg.omega2, U0)
+    x = hp.Op1D(cfg.nx, cfg.px, cfg.ax, cfg.bx, cfg.bc)
+    y = hp.Op1D(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc)
+    o = hp.hpadi_options()
+    o.lines_per_block = lw
+    o.col_lines_per_block = clw
+    for prec in ("mixed", "fp64"):
+        plan = hp.Plan(x, y, cfg.omega2, cfg.tol, prec, options=o)
+        U, st = plan.solve(torch.from_numpy(G0).cuda())
+        err = oadi.rel_l2_error(U.cpu().numpy(), U0, ox, oy)
+        print(f"  {prec}: rounds={st.rounds} err={err:.2e}", flush=True)
+        assert st.status == hp.HPADI_OK and err <= cfg.tol
+        plan.close()
