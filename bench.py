@@ -262,7 +262,7 @@ def main():
     launches_per_step = ct[dom] / (args.steps + args.warmup)
     cl = cfgD.px // 2
     roof = {"bound": "hbm",
-            "kernel": f"sweep_uni_kernel<float, float, {cl}, 0, true, 8> (full column half-sweep)",
+            "kernel": f"sweep_uni_kernel<float, float, {cl}, 0, true, 4> (full column half-sweep)",
             "achieved": by[dom] / (ms[dom] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "traffic": measured_traffic(),
             "bytes_per_launch": by[dom] / ct[dom], "avg_launch_us": ms[dom] / ct[dom] * 1e3,

@@ -79,7 +79,7 @@ typedef struct {
 typedef struct {
     double inner_tol;   /* mixed mode: tolerance of the shift family of every round (0 = 3e-6) */
     int max_rounds;     /* mixed mode: refinement round limit (0 = 8) */
-    int lines_per_block; /* half-sweep workgroup width: 1, 4 or 8 lines (0 = 8); 1 needs n % 64 == 0 on
+    int lines_per_block; /* half-sweep workgroup width: 1, 4 or 8 lines (0 = 4); 1 needs n % 64 == 0 on
                             that axis (else 8); 4 also selects 4-column panels in the internal layout */
     int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
     int fp32_rounds;    /* mixed mode: leading rounds with FP32 sweeps; later rounds are FP64 (0 = 1) */

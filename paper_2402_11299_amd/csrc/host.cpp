@@ -968,9 +968,10 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     const int Nx = x->N, Ny = y->N;
     P->ldw = ((long)Ny + 63) / 64 * 64;
     hpadi::Layout& L = P->lint;
-    // panel width of the internal layout: 4 when 4-line workgroups are asked for, else 8;
-    // lines per workgroup of the ADI half-sweeps: 1, 4 or 8 per direction
-    const int pw = P->opt.lines_per_block == 4 ? 4 : 8;
+    // panel width of the internal layout: 8 when 8-line (or 1-line) workgroups are asked
+    // for, else 4 (measured fastest for FP64 at n = p = 64, equal for FP32); lines per
+    // workgroup of the ADI half-sweeps: 1, 4 or 8 per direction
+    const int pw = (P->opt.lines_per_block == 8 || P->opt.lines_per_block == 1) ? 8 : 4;
     auto lines = [&](int req, int n_line_axis) {
         if (req == 1 && n_line_axis % 64 == 0) return 1;
         return pw;
@@ -1200,7 +1201,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     // one fixed-schedule solve of each candidate on the instance's own data
     std::vector<std::pair<std::vector<int>, int>> tuned;
     B->plans.assign(count, nullptr);
-    B->lw.assign(count, 8);
+    B->lw.assign(count, 4);
     B->G.assign(G, G + count);
     B->U.assign(U, U + count);
     B->ldg.assign(ldg, ldg + count);
@@ -1218,7 +1219,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     };
     for (int i = 0; i < count; ++i) {
         const std::vector<int> key = {xs[i]->n, xs[i]->p, ys[i]->n, ys[i]->p, xs[i]->bc};
-        int lw = 8;
+        int lw = 4;
         bool found = false;
         for (auto& kv : tuned)
             if (kv.first == key) {
@@ -1228,7 +1229,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         int rc = HPADI_OK;
         if (!found && autotune) {
             double best = 1e300;
-            for (int cand : {8, 4}) {
+            for (int cand : {4, 8}) {
                 hpadi_plan pl = nullptr;
                 if ((rc = make_plan(i, cand, &pl)) != HPADI_OK) {
                     hpadi_plan_destroy(pl);

@@ -105,7 +105,7 @@ hipError_t launch_coef_tables(const DimDev& d, int nf, const double* facS, int s
 //   5 a1 = M.invd(m) (kappa K_mm + tau M_mm)   6 a2 = M.invd(m) tau M_{m-2,m}
 //   7 a3 = M.invd(m) tau M_{m,m+2}             8 a4 = -M.invd(m) M.link(m+2)
 //   9 f1 = M.invd(m)               10 f2 = -M.link(m) M.invd(m)   11 t2 = -M.link(m+2) M.invd(m)
-//   12 M.invd(m) tau delta (head term), 13..15 unused.
+//   12 M.invd(m) tau delta (head term), 13 M_mm (diagonal of M), 14..15 unused.
 hipError_t launch_pass_tables(const DimDev& d, int nf, const double* facS, int stride, const double* facM,
                               FactorLayout fl, const double* tau_dev, double kappa, double* out, hipStream_t s);
 int sweep_threads(int n, int lines_per_block);

@@ -550,6 +550,7 @@ __global__ void pass_table_kernel(DimDev d, const double* facS, int stride, cons
         r[10] = -mlnk * minv;
         r[11] = -mlnk_up * minv;
         r[12] = minv * tau * de;
+        r[13] = md[m] * de;  // diagonal of M at degree m (weights of the norm estimates)
     }
 }
 }  // namespace

@@ -214,28 +214,41 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
         // product v = (kappa K + tau M) x and u = Lm^{-T} v on the chains, highest degree
         // first; a bubble entry of u is final once computed (the hat block of Lm^T does not
         // feed back into the bubbles), so g - u is stored as it is produced.
+        // G~ of the chain is loaded ahead of the recurrence (all of it for FP32, in two
+        // halves for FP64), so the loads do not wait one by one behind the output stores.
+        constexpr int PF = (sizeof(TIN) == 4 || CL < 16) ? CL : CL / 2;
+        TIN gv[CL];
+        const char* gb = reinterpret_cast<const char*>(a.g);
+        unsigned og0, sg;
+        chain0(a.lg, og0, sg, sizeof(TIN));
+        auto load_g = [&](int s) {
+            // the phantom step and inactive lanes read the array's first entry (unused)
+            const bool real = act && (s < CL - 1 || full);
+            gv[s] = *reinterpret_cast<const TIN*>(gb + (real ? og0 + (unsigned)s * sg : 0u));
+        };
+#pragma unroll
+        for (int s = CL - PF; s < CL; ++s) load_g(s);
         if (act) {
-            const char* gb = reinterpret_cast<const char*>(a.g);
             char* ob = reinterpret_cast<char*>(a.out);
-            unsigned og, sg, oo, so;
-            chain0(a.lg, og, sg, sizeof(TIN));
+            unsigned oo, so;
             chain0(a.lout, oo, so, sizeof(TOUT));
-            og += (CL - 1) * sg;
             oo += (CL - 1) * so;
             const double hterm = pi == 0 ? (xl + xr) * (1.0 / 6.0) : (xr - xl) * (1.0 / 30.0);
             double x_n = 0.0, u_n = 0.0;
             // u_s = a1 x_s + a2 x_{s-1} + a3 x_{s+1} + a4 u_{s+1} (+ the hat term at the head)
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
+                if (PF < CL && s == CL - PF) {
+#pragma unroll
+                    for (int s2 = 0; s2 < CL - PF; ++s2) load_g(s2);
+                }
                 const int m = pi + 2 * s;
                 const double x = y[s];
                 double u = PT(m, 5) * x;
                 if (s > 0) u += PT(m, 6) * y[s - 1];
                 if (s + 1 < CL) u += PT(m, 7) * x_n + PT(m, 8) * u_n;
                 if (s == 0) u += PT(m, 12) * hterm;
-                if (s < CL - 1 || full)
-                    *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)((double)*reinterpret_cast<const TIN*>(gb + og) - u);
-                og -= sg;
+                if (s < CL - 1 || full) *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)((double)gv[s] - u);
                 oo -= so;
                 x_n = x;
                 u_n = u;
@@ -326,31 +339,41 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev
             double prev = 0.0;
             double* out = reinterpret_cast<double*>(a.out);
             char* ob = reinterpret_cast<char*>(a.out);
-            const double* w = d.mdiag;
-            unsigned o, st;
-            chain0(a.lout, o, st, sizeof(double));
+            unsigned o0, st;
+            chain0(a.lout, o0, st, sizeof(double));
+            // previous U of the chain, loaded in two halves ahead of the stores
+            constexpr int PH = CL < 16 ? CL : CL / 2;
+            double uo[CL];
+            auto load_u = [&](int s) {
+                const bool real = a.accumulate && (s < CL - 1 || full);
+                uo[s] = real ? *reinterpret_cast<const double*>(ob + o0 + (unsigned)s * st) : 0.0;
+            };
+#pragma unroll
+            for (int s = 0; s < PH; ++s) load_u(s);
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
+                if (PH < CL && s == PH / 2) {
+#pragma unroll
+                    for (int s2 = PH; s2 < CL; ++s2) load_u(s2);
+                }
                 const int m = pi + 2 * s;
                 if (s == 0) prev = (y[0] - FM.cpl[4 * e + 2 * pi] * xl - FM.cpl[4 * e + 2 * pi + 1] * xr) * PT(m, 9);
                 else prev = PT(m, 9) * y[s] + PT(m, 10) * prev;
                 if (s < CL - 1 || full) {
-                    const int pos = nh + 2 * s * n + c;
-                    double* po = reinterpret_cast<double*>(ob + o);
-                    const double u = a.accumulate ? *po + prev : prev;
-                    *po = u;
-                    sdx += w[pos] * prev * prev;
-                    su += w[pos] * u * u;
+                    const double u = uo[s] + prev;
+                    *reinterpret_cast<double*>(ob + o0 + (unsigned)s * st) = u;
+                    const double wm = PT(m, 13);
+                    sdx += wm * prev * prev;
+                    su += wm * u * u;
                 }
-                o += st;
             }
             if (c < nh) {
                 const long oh = IDX(a.lout, line, c);
                 const double dx = A[c];
                 const double u = a.accumulate ? out[oh] + dx : dx;
                 out[oh] = u;
-                sdx += w[c] * dx * dx;
-                su += w[c] * u * u;
+                sdx += d.mdiag[c] * dx * dx;
+                su += d.mdiag[c] * u * u;
             }
             if (a.norm_acc) {
                 const double wl = a.wline[line];
