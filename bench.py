@@ -170,6 +170,66 @@ def varcoef_fcg(hp, torch, steps=3):
             **res}
 
 
+def learned_fcg(hp, torch, nfield=9, steps=2000, crop=128):
+    """The learned correction on the variable-coefficient workload (n = p = 32): training
+    pairs from plain ADI-PCG iterates on nfield coefficient fields (two Gaussian random fields
+    for every singular one), Adam training on the GPU, then a held-out Gaussian random field:
+    plain ADI-PCG against flexible CG with the correction, both to 1e-10."""
+    import numpy as np
+    import workloads
+    n = p = 32
+    x = hp.Op1D(n, p, 0.0, 1.0, "dirichlet")
+    y = hp.Op1D(n, p, 0.0, 1.0, "dirichlet")
+    xs, _ = hp.VarCoef.grid(x)
+    ys, _ = hp.VarCoef.grid(y)
+    pre = hp.Plan(x, y, 0.0, 1e-4, "fp64")
+
+    def field(kind, seed):
+        a = (workloads.grf_coefficient(xs, ys, seed=seed) if kind == "grf"
+             else workloads.singular_coefficient(xs, ys, workloads.singular_x0(seed)))
+        return hp.VarCoef(x, y, torch.from_numpy(a).cuda())
+
+    t0 = time.perf_counter()
+    parts = []
+    for i in range(nfield):
+        vc = field("grf" if i % 3 != 2 else "singular", 100 + i)
+        b = pre.load(torch.from_numpy(workloads.legendre_rhs(n, p, n, p, seed=200 + i)).cuda())
+        xstar, _, _ = vc.solve(b, pre, tol=1e-13, maxit=400, truncation=0)
+        parts.append([t.clone() for t in vc.pairs(pre, b, xstar, crop=crop, crops_per_iter=6, cap=400, seed=i)])
+        vc.close()
+    X, ZN, T, W = [torch.cat([q[k] for q in parts]).contiguous() for k in range(4)]
+    t_pairs = time.perf_counter() - t0
+    zero = hp.Net(np.zeros(hp.lib().hpadi_net_num_params(), dtype=np.float32))
+    L0, _ = zero.loss_grad(X[:32].contiguous(), ZN[:32].contiguous(), T[:32].contiguous(), W[:32].contiguous())
+    zero.close()
+    net = hp.Net(seed=1)
+    t0 = time.perf_counter()
+    hist = net.train(X, ZN, T, W, batch=8, steps=steps, lr=1e-3, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    L1, _ = net.loss_grad(X[:32].contiguous(), ZN[:32].contiguous(), T[:32].contiguous(), W[:32].contiguous())
+    vc = field("grf", 300)
+    b = pre.load(torch.from_numpy(workloads.legendre_rhs(n, p, n, p, seed=700)).cuda())
+    res = {}
+    for name, m, nn in (("plain_pcg", 0, None), ("learned_fcg1", 1, net)):
+        vc.solve(b, pre, tol=1e-10, maxit=400, truncation=m, net=nn)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st, _ = vc.solve(b, pre, tol=1e-10, maxit=400, truncation=m, net=nn)
+        torch.cuda.synchronize()
+        res[name] = {"iters": st.iters, "ms": (time.perf_counter() - t1) * 1e3, "true_rel_res": st.true_rel_res,
+                     "corrections": st.corrections}
+    log(f"learned: {X.shape[0]} pairs ({t_pairs:.1f} s), train {steps} steps {t_train:.1f} s, loss (plain z) {L0:.3f} "
+        f"-> {L1:.3f}; held-out: pcg {res['plain_pcg']['iters']} it {res['plain_pcg']['ms']:.1f} ms, "
+        f"learned {res['learned_fcg1']['iters']} it {res['learned_fcg1']['ms']:.1f} ms")
+    vc.close()
+    pre.close()
+    net.close()
+    return {"workload": "varcoef_n32_p32: training on ADI-PCG iterates of 9 fields, held-out Gaussian random field",
+            "pairs": int(X.shape[0]), "crop": crop, "train_steps": steps, "train_s": t_train, "pairs_s": t_pairs,
+            "loss_plain_z": L0, "loss_trained": L1, "loss_last50": float(np.mean(hist[-50:])), **res}
+
+
 def batch_solve(hp, torch, steps=3, count=512):
     """512 independent screened-Poisson solves (per axis n in {4..64}, p in {8..128}, N <= 2049,
     omega^2 log-uniform in [1e-2, 1e3], random BC) replayed as one graph; G per instance a
@@ -311,6 +371,7 @@ def main():
     if not args.only_mixed:
         out["varcoef_fcg"] = varcoef_fcg(hp, torch)
         out["batch"] = batch_solve(hp, torch)
+        out["learned_correction"] = learned_fcg(hp, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
