@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # to the value recorded with it.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_uni_col_fp32_n64_p64.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2402_11299_amd", "csrc", f)
-                  for f in ("sweep_uni.hip", "sweep_common.h", "internal.h")]
+                  for f in ("sweep_uni.hip", "sweep_uni_body.h", "sweep_common.h", "internal.h")]
 
 
 def log(*a):
@@ -247,7 +247,7 @@ def batch_solve(hp, torch, steps=3, count=512):
         Us.append(torch.empty_like(G))
         dofs += x.N * y.N
     t0 = time.perf_counter()
-    b = hp.Batch(probs, 1e-10, Gs, Us, autotune=True, nstreams=8)
+    b = hp.Batch(probs, 1e-10, Gs, Us, autotune=True)
     t_create = time.perf_counter() - t0
     b.solve()
     torch.cuda.synchronize()

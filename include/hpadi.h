@@ -173,14 +173,17 @@ void hpadi_plan_destroy(hpadi_plan plan);
 /* count independent problems A_Y^x U M^y + M^x U A_Y^y = G (operators xs[i],
  * ys[i], omega2[i]; any sizes, degrees and boundary conditions) solved to the
  * relative error tol, replayed as one HIP graph.  Each instance has a MIXED plan
- * and a fixed schedule of one round with FP32 storage and one FP64 round; the
- * instances are spread over nstreams (0 = 8) concurrent capture streams,
- * largest first onto the least loaded stream (work estimate N_x N_y log(N_x N_y)).
+ * and a fixed schedule of one round with FP32 storage and one FP64 round.  The
+ * instances advance in lock step: every ADI iteration is a few grouped launches,
+ * one per (direction, chain length p/2, lines per workgroup) present, each running
+ * that half-sweep for all instances in it (a device task table maps workgroups to
+ * instances); transforms and final solves likewise; residuals per instance.
  * autotune != 0: for every distinct (n_x, p_x, n_y, p_y, bc) the lines per
  * workgroup (4 or 8) is chosen by timing both on the instance (this runs solves
  * and overwrites U[i]).  G[i], U[i]: FP64 device arrays N_x x N_y (ld ldg[i],
  * ldu[i]) bound to the graph: later solves read and write these same arrays.
- * hip_stream: the stream the graph is launched on (a hipStream_t or NULL). */
+ * nstreams: reserved, pass 0.  hip_stream: the stream the graph is launched on (a
+ * hipStream_t, or NULL for a stream of the batch's own). */
 typedef struct hpadi_batch_s* hpadi_batch;
 int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, const double* omega2, double tol,
                        const double* const* G, const int* ldg, double* const* U, const int* ldu, int autotune,
@@ -190,7 +193,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
  * rounds outside the graph (*n_extra counts them; may be NULL).  stats: host
  * array of count entries or NULL.  ENOCONV if an instance stays above tol. */
 int hpadi_batch_solve(hpadi_batch b, hpadi_stats* stats, int* n_extra);
-/* Tuned lines per workgroup, J and capture stream of instance i (any pointer may be NULL). */
+/* Tuned lines per workgroup and J of instance i; stream_index is 0 (any pointer may be NULL). */
 int hpadi_batch_info(hpadi_batch b, int i, int* lines_per_block, int* J, int* stream_index);
 void hpadi_batch_destroy(hpadi_batch b);
 

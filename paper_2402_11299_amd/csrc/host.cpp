@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -457,7 +458,7 @@ int make_dim(DimHost& D, const hpadi_op1d_s& o) {
     D.dev.tabstride = ts;
     D.hpad = (o.nh + 7) / 8 * 8;
     D.Npad = D.hpad + (p - 1) * n;
-    D.uniform = n % 8 == 0;
+    D.uniform = n % 4 == 0;
     for (int e = 1; e < n && D.uniform; ++e) D.uniform = o.delta[e] == o.delta[0];
     return HPADI_OK;
 }
@@ -574,71 +575,90 @@ hpadi::SweepArgs sweep_args(const hpadi_plan_s* P, bool column, int j) {
     const double* ptab = column ? P->ptabx : P->ptaby;
     a.ptab = ptab ? ptab + (size_t)(j < P->J ? j : 0) * D.op.p * 16 : nullptr;
     a.lpb = column ? P->lpb_col : P->lpb_row;
-    a.idx32 = P->nint < (size_t(1) << 31) ? 1 : 0;
+    // byte offsets of 8-byte entries must fit the 32-bit offsets of the uniform kernel
+    a.idx32 = P->nint < (size_t(1) << 29) ? 1 : 0;
     return a;
 }
 
-// G~ = V^{-T} R L^{-1}: column then row transform (mass factors M^x = V^T V, M^y = L^T L).
-int transform_rhs(hpadi_plan_s* P, const double* R, long ldr, int ts) {
-    const double dofs = (double)P->dx.op.N * P->dy.op.N;
+// Arguments of the transform passes (column: R -> T64; row: T64 -> G~ in ts bytes).
+hpadi::SweepArgs transform_col_args(const hpadi_plan_s* P, const double* R, long ldr) {
     hpadi::SweepArgs c = sweep_args(P, true, P->J);
     c.in = R;
     c.lin = user_layout(P, ldr);
-    if ((double)ldr * P->dx.op.N >= 2147483648.0) c.idx32 = 0;
+    if ((double)ldr * P->dx.op.N >= 536870912.0) c.idx32 = 0;
     c.out = P->T64;
     c.lout = P->lint;
-    int rc = timed_sweep(P, true, c, hpadi::SWEEP_TRANSFORM, 8, 8, 2, dofs * 16.0);
-    if (rc != HPADI_OK) return rc;
+    return c;
+}
+hpadi::SweepArgs transform_row_args(const hpadi_plan_s* P) {
     hpadi::SweepArgs r = sweep_args(P, false, P->J);
     r.in = P->T64;
     r.lin = P->lint;
     r.out = P->Gt;
     r.lout = P->lint;
-    return timed_sweep(P, false, r, hpadi::SWEEP_TRANSFORM, 8, ts, 2, dofs * (8.0 + ts));
+    return r;
+}
+// Arguments of the ADI half-sweeps of iteration j (row: shift q_j; column: p_{j+1}).
+hpadi::SweepArgs adi_row_args(const hpadi_plan_s* P, int j) {
+    hpadi::SweepArgs r = sweep_args(P, false, j);
+    r.in = j == 0 ? P->Gt : P->Wk;
+    r.lin = P->lint;
+    r.g = P->Gt;
+    r.lg = P->lint;
+    r.out = P->Wk;
+    r.lout = P->lint;
+    r.kappa = 1.0;
+    r.tau = P->omega2 / 2.0 + P->Q[j];
+    return r;
+}
+hpadi::SweepArgs adi_col_args(const hpadi_plan_s* P, int j) {
+    hpadi::SweepArgs c = sweep_args(P, true, j);
+    c.in = P->Wk;
+    c.lin = P->lint;
+    c.g = P->Gt;
+    c.lg = P->lint;
+    c.out = P->Wk;
+    c.lout = P->lint;
+    c.kappa = 1.0;
+    c.tau = j + 1 == P->J ? 0.0 : P->omega2 / 2.0 - P->P[j + 1];
+    return c;
+}
+// Arguments of the final mass solve U (+)= L^{-1} w.
+hpadi::SweepArgs final_args(const hpadi_plan_s* P, double* U, long ldu, bool accumulate) {
+    hpadi::SweepArgs f = sweep_args(P, false, P->J);
+    f.in = P->Wk;
+    f.lin = P->lint;
+    f.out = U;
+    f.lout = user_layout(P, ldu);
+    if ((double)ldu * P->dx.op.N >= 536870912.0) f.idx32 = 0;
+    f.accumulate = accumulate ? 1 : 0;
+    f.norm_acc = accumulate ? P->acc : nullptr;
+    f.wline = P->dx.dev.mdiag;
+    return f;
+}
+
+// G~ = V^{-T} R L^{-1}: column then row transform (mass factors M^x = V^T V, M^y = L^T L).
+int transform_rhs(hpadi_plan_s* P, const double* R, long ldr, int ts) {
+    const double dofs = (double)P->dx.op.N * P->dy.op.N;
+    int rc = timed_sweep(P, true, transform_col_args(P, R, ldr), hpadi::SWEEP_TRANSFORM, 8, 8, 2, dofs * 16.0);
+    if (rc != HPADI_OK) return rc;
+    return timed_sweep(P, false, transform_row_args(P), hpadi::SWEEP_TRANSFORM, 8, ts, 2, dofs * (8.0 + ts));
 }
 
 // Alg. 2 solve loop in balanced coordinates, from G~ (in P->Gt) to U (user layout):
 // U = u (FP64 mode) or U += u (refinement rounds).
 int run_adi(hpadi_plan_s* P, int ts, double* U, long ldu, bool accumulate) {
     const double dofs = (double)P->dx.op.N * P->dy.op.N;
-    const double half = P->omega2 / 2.0;
-    const hpadi::Layout L = P->lint;
     for (int j = 0; j < P->J; ++j) {
-        hpadi::SweepArgs r = sweep_args(P, false, j);
-        r.in = j == 0 ? P->Gt : P->Wk;
-        r.lin = L;
-        r.g = P->Gt;
-        r.lg = L;
-        r.out = P->Wk;
-        r.lout = L;
-        r.kappa = 1.0;
-        r.tau = half + P->Q[j];
-        int rc = timed_sweep(P, false, r, hpadi::SWEEP_FULL, ts, ts, 1, dofs * 3.0 * ts);
+        int rc = timed_sweep(P, false, adi_row_args(P, j), hpadi::SWEEP_FULL, ts, ts, 1, dofs * 3.0 * ts);
         if (rc != HPADI_OK) return rc;
-        hpadi::SweepArgs c = sweep_args(P, true, j);
-        c.in = P->Wk;
-        c.lin = L;
-        c.g = P->Gt;
-        c.lg = L;
-        c.out = P->Wk;
-        c.lout = L;
-        c.kappa = 1.0;
         const bool last = j + 1 == P->J;
-        c.tau = last ? 0.0 : half - P->P[j + 1];
-        rc = timed_sweep(P, true, c, last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts, last ? 2 : 0,
-                         dofs * (last ? 2.0 : 3.0) * ts);
+        rc = timed_sweep(P, true, adi_col_args(P, j), last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts,
+                         last ? 2 : 0, dofs * (last ? 2.0 : 3.0) * ts);
         if (rc != HPADI_OK) return rc;
     }
-    hpadi::SweepArgs f = sweep_args(P, false, P->J);
-    f.in = P->Wk;
-    f.lin = L;
-    f.out = U;
-    f.lout = user_layout(P, ldu);
-    if ((double)ldu * P->dx.op.N >= 2147483648.0) f.idx32 = 0;
-    f.accumulate = accumulate ? 1 : 0;
-    f.norm_acc = accumulate ? P->acc : nullptr;
-    f.wline = P->dx.dev.mdiag;
-    return timed_sweep(P, false, f, hpadi::SWEEP_FINAL, ts, 8, 2, dofs * (ts + (accumulate ? 16.0 : 8.0)));
+    return timed_sweep(P, false, final_args(P, U, ldu, accumulate), hpadi::SWEEP_FINAL, ts, 8, 2,
+                       dofs * (ts + (accumulate ? 16.0 : 8.0)));
 }
 
 // T1 = U M_y, T2 = U A_y (row operators, FP64).
@@ -713,6 +733,92 @@ int enqueue_fixed_solve(hpadi_plan_s* P, const double* G, long ldg, double* U, l
 
 }  // namespace
 
+namespace {
+
+// One launch of a batch schedule.
+struct BatchStep {
+    int kind = 0;        // 0 grouped sweep, 1 single sweep, 2 residual, 3 zero U, 4 zero accumulators
+    hpadi::GroupLaunch g{};
+    size_t task_off = 0;
+    int inst = -1;
+    hpadi::SweepArgs a{};
+    int mode = 0, tin = 8, tout = 8;
+    bool column = false;
+};
+
+// Appends the half-sweeps of one kind for the listed instances: those the uniform-mesh
+// kernel takes are grouped by (chain length, lines per workgroup, n) into one launch each,
+// the others are launched one by one.
+void add_sweeps(std::vector<BatchStep>& steps, std::vector<hpadi::GroupTask>& table,
+                const std::vector<hpadi_plan>& plans, const std::vector<std::pair<int, hpadi::SweepArgs>>& items,
+                int mode, int tin, int tout, bool column) {
+    // (chain length, lines per workgroup, n) -> item indices: equal n keeps the workgroup
+    // size of a launch exact
+    std::vector<std::pair<std::array<int, 3>, std::vector<int>>> groups;
+    for (size_t k = 0; k < items.size(); ++k) {
+        const hpadi_plan_s* P = plans[items[k].first];
+        const hpadi::DimDev& d = column ? P->dx.dev : P->dy.dev;
+        const hpadi::SweepArgs& a = items[k].second;
+        if (a.nlines <= 0) continue;
+        const bool uni = a.ptab && a.idx32 && (a.lpb == 4 || a.lpb == 8 || a.lpb == 16) &&
+                         hpadi::sweep_uni_available(d, a.lpb) &&
+                         (int)hpadi::sweep_uni_threads(d, a.lpb) <= hpadi::sweep_uni_max_threads(d.p / 2);
+        if (!uni) {
+            BatchStep st;
+            st.kind = 1;
+            st.inst = items[k].first;
+            st.a = a;
+            st.mode = mode;
+            st.tin = tin;
+            st.tout = tout;
+            st.column = column;
+            steps.push_back(st);
+            continue;
+        }
+        const std::array<int, 3> key{d.p / 2, a.lpb, d.n};
+        auto it = std::find_if(groups.begin(), groups.end(), [&](const auto& g) { return g.first == key; });
+        if (it == groups.end()) groups.push_back({key, {(int)k}});
+        else it->second.push_back((int)k);
+    }
+    for (auto& grp : groups) {
+        BatchStep st;
+        st.kind = 0;
+        st.task_off = table.size();
+        hpadi::GroupLaunch& g = st.g;
+        g.mode = mode;
+        g.tin = tin;
+        g.tout = tout;
+        g.cl = grp.first[0];
+        g.lw = grp.first[1];
+        g.column = column;
+        int blocks = 0, threads = 0;
+        for (int k : grp.second) {
+            const hpadi_plan_s* P = plans[items[k].first];
+            const hpadi::DimDev& d = column ? P->dx.dev : P->dy.dev;
+            hpadi::GroupTask t{};
+            t.d = d;
+            t.a = items[k].second;
+            t.block0 = blocks;
+            t.nblk = (t.a.hpad_lines + t.a.nlines - t.a.nh_lines + g.lw - 1) / g.lw;
+            blocks += t.nblk;
+            threads = std::max(threads, (int)hpadi::sweep_uni_threads(d, g.lw));
+            table.push_back(t);
+        }
+        size_t lds = 0;
+        for (int k : grp.second) {
+            const hpadi_plan_s* P = plans[items[k].first];
+            lds = std::max(lds, hpadi::sweep_uni_lds_bytes(column ? P->dx.dev : P->dy.dev, g.lw, threads, mode));
+        }
+        g.ntasks = (int)grp.second.size();
+        g.nblocks = blocks;
+        g.threads = threads;
+        g.lds_bytes = lds;
+        steps.push_back(st);
+    }
+}
+
+}  // namespace
+
 // ===========================================================================
 // Batched solves: independent plans replayed as one graph.
 // ===========================================================================
@@ -721,12 +827,13 @@ struct hpadi_batch_s {
     std::vector<hpadi_plan> plans;
     std::vector<const double*> G;
     std::vector<double*> U;
-    std::vector<int> ldg, ldu, lw, stream_of;
-    std::vector<hipStream_t> side;
+    std::vector<int> ldg, ldu, lw;
     hipStream_t origin = nullptr;
     bool own_origin = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hpadi::GroupTask* table = nullptr;   // device task tables of the grouped launches
+    int nlaunch = 0;                     // launches in the graph
     double tol = 0.0;
     const double** acc_ptrs = nullptr;   // device array of the plans' accumulators
     double* acc_all = nullptr;           // device [count][2]
@@ -736,10 +843,10 @@ struct hpadi_batch_s {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (hpadi_plan p : plans) hpadi_plan_destroy(p);
-        for (hipStream_t st : side) (void)hipStreamDestroy(st);
         if (own_origin) (void)hipStreamDestroy(origin);
         (void)hipFree(acc_ptrs);
         (void)hipFree(acc_all);
+        (void)hipFree(table);
         if (acc_host) (void)hipHostFree(acc_host);
     }
 };
@@ -974,6 +1081,8 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     const int pw = (P->opt.lines_per_block == 8 || P->opt.lines_per_block == 1) ? 8 : 4;
     auto lines = [&](int req, int n_line_axis) {
         if (req == 1 && n_line_axis % 64 == 0) return 1;
+        // a wavefront holds 64 / lines chains of one parity: small n needs more lines
+        if (n_line_axis % (64 / pw) != 0 && n_line_axis % 4 == 0) return 16;
         return pw;
     };
     // a column pass runs along x (chains of the x basis), a row pass along y
@@ -1167,36 +1276,12 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         }
         B->own_origin = true;
     }
-    const int S = std::max(1, std::min(nstreams > 0 ? nstreams : 8, count));
-    for (int i = 0; i < S; ++i) {
-        hipStream_t st = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            delete B;
-            return HPADI_EHIP;
-        }
-        B->side.push_back(st);
-    }
-    // longest work first onto the least loaded stream (work ~ J N_x N_y, J ~ log of the
-    // spectral ratio: use N_x N_y log(N_x N_y) as the estimate)
-    std::vector<int> order(count);
-    std::vector<double> work(count);
-    for (int i = 0; i < count; ++i) {
+    (void)nstreams;
+    for (int i = 0; i < count; ++i)
         if (!xs[i] || !ys[i]) {
             delete B;
             return HPADI_EINVAL;
         }
-        const double d = (double)xs[i]->N * ys[i]->N;
-        work[i] = d * std::log(2.0 + d);
-        order[i] = i;
-    }
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
-    std::vector<double> load(S, 0.0);
-    B->stream_of.assign(count, 0);
-    for (int i : order) {
-        const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        B->stream_of[i] = st;
-        load[st] += work[i];
-    }
     // autotuner: lines per workgroup (4 or 8) per distinct (n_x, p_x, n_y, p_y, bc), by timing
     // one fixed-schedule solve of each candidate on the instance's own data
     std::vector<std::pair<std::vector<int>, int>> tuned;
@@ -1209,8 +1294,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     auto make_plan = [&](int i, int lw, hpadi_plan* pl) -> int {
         hpadi_options o{};
         o.lines_per_block = lw;
-        int rc = hpadi_plan_create_ex(xs[i], ys[i], omega2[i], tol, HPADI_MIXED, nullptr, B->side[B->stream_of[i]],
-                                      &o, pl);
+        int rc = hpadi_plan_create_ex(xs[i], ys[i], omega2[i], tol, HPADI_MIXED, nullptr, B->origin, &o, pl);
         if (rc != HPADI_OK) return rc;
         hpadi_plan_s* P = *pl;
         if ((rc = ensure_fp64_work(P)) != HPADI_OK) return rc;
@@ -1279,26 +1363,87 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         delete B;
         return HPADI_ENOMEM;
     }
-    // capture: origin -> every side stream -> instances in load order -> join -> gather accumulators
-    hipEvent_t fork = nullptr;
-    std::vector<hipEvent_t> joins(S, nullptr);
-    bool ok = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
-    for (int k = 0; ok && k < S; ++k) ok = hipEventCreateWithFlags(&joins[k], hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed) == hipSuccess;
-    ok = ok && hipEventRecord(fork, B->origin) == hipSuccess;
-    for (int k = 0; ok && k < S; ++k) ok = hipStreamWaitEvent(B->side[k], fork, 0) == hipSuccess;
-    for (int i : order) {
-        if (!ok) break;
-        ok = enqueue_fixed_solve(B->plans[i], G[i], ldg[i], U[i], ldu[i], 1, 1) == HPADI_OK;
+    // the schedule: both rounds of every instance in lock step, every kind of half-sweep
+    // of one iteration as few grouped launches as there are (chain length, width) pairs
+    std::vector<BatchStep> steps;
+    std::vector<hpadi::GroupTask> table;
+    int jmax = 0;
+    for (int i = 0; i < count; ++i) jmax = std::max(jmax, B->plans[i]->J);
+    for (int round = 1; round <= 2; ++round) {
+        const int ts = round == 1 ? 4 : 8;
+        for (int i = 0; i < count; ++i) {
+            BatchStep st;
+            st.inst = i;
+            st.kind = round == 1 ? 3 : 2;
+            steps.push_back(st);
+            st.kind = 4;
+            steps.push_back(st);
+        }
+        std::vector<std::pair<int, hpadi::SweepArgs>> items;
+        for (int i = 0; i < count; ++i) {
+            hpadi_plan_s* P = B->plans[i];
+            items.push_back({i, transform_col_args(P, round == 1 ? G[i] : P->R64, round == 1 ? ldg[i] : P->ldw)});
+        }
+        add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, 8, true);
+        items.clear();
+        for (int i = 0; i < count; ++i) items.push_back({i, transform_row_args(B->plans[i])});
+        add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, ts, false);
+        for (int jj = 0; jj < jmax; ++jj) {
+            std::vector<std::pair<int, hpadi::SweepArgs>> rows, cols, last;
+            for (int i = 0; i < count; ++i) {
+                hpadi_plan_s* P = B->plans[i];
+                if (jj >= P->J) continue;
+                rows.push_back({i, adi_row_args(P, jj)});
+                (jj + 1 == P->J ? last : cols).push_back({i, adi_col_args(P, jj)});
+            }
+            add_sweeps(steps, table, B->plans, rows, hpadi::SWEEP_FULL, ts, ts, false);
+            add_sweeps(steps, table, B->plans, cols, hpadi::SWEEP_FULL, ts, ts, true);
+            add_sweeps(steps, table, B->plans, last, hpadi::SWEEP_SOLVE, ts, ts, true);
+        }
+        items.clear();
+        for (int i = 0; i < count; ++i) items.push_back({i, final_args(B->plans[i], U[i], ldu[i], true)});
+        add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_FINAL, ts, 8, false);
     }
-    for (int k = 0; ok && k < S; ++k)
-        ok = hipEventRecord(joins[k], B->side[k]) == hipSuccess && hipStreamWaitEvent(B->origin, joins[k], 0) == hipSuccess;
+    if (!table.empty() &&
+        (dmalloc(&B->table, table.size()) != hipSuccess ||
+         hipMemcpy(B->table, table.data(), table.size() * sizeof(hpadi::GroupTask), hipMemcpyHostToDevice) != hipSuccess)) {
+        delete B;
+        return HPADI_ENOMEM;
+    }
+    // capture the schedule on the origin stream (every plan works on that stream)
+    for (hpadi_plan p : B->plans) p->stream = B->origin;
+    bool ok = hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed) == hipSuccess;
+    for (const BatchStep& st : steps) {
+        if (!ok) break;
+        hpadi_plan_s* P = st.inst >= 0 ? B->plans[st.inst] : nullptr;
+        switch (st.kind) {
+            case 0: {
+                hpadi::GroupLaunch g = st.g;
+                g.tasks = B->table + st.task_off;
+                ok = hpadi::launch_sweep_uni_grouped(g, B->origin) == hipSuccess;
+                break;
+            }
+            case 1:
+                ok = hpadi::launch_sweep(st.column ? P->dx.dev : P->dy.dev, st.a, st.mode, st.tin, st.tout, st.column,
+                                         B->origin) == hipSuccess;
+                break;
+            case 2:
+                ok = residual_into_r64(P, G[st.inst], ldg[st.inst], U[st.inst], ldu[st.inst]) == HPADI_OK;
+                break;
+            case 3:
+                ok = hpadi::launch_zero_f64(U[st.inst], ldu[st.inst], P->dx.op.N, P->dy.op.N, B->origin) == hipSuccess;
+                break;
+            case 4:
+                ok = hpadi::launch_zero_f64(P->acc, 2, 1, 2, B->origin) == hipSuccess;
+                break;
+            default:
+                ok = false;
+        }
+        ++B->nlaunch;
+    }
     ok = ok && hpadi::launch_gather_acc(B->acc_ptrs, count, B->acc_all, B->origin) == hipSuccess;
     const bool ended = hipStreamEndCapture(B->origin, &B->graph) == hipSuccess;
     ok = ok && ended && hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) == hipSuccess;
-    if (fork) (void)hipEventDestroy(fork);
-    for (hipEvent_t e : joins)
-        if (e) (void)hipEventDestroy(e);
     if (!ok) {
         delete B;
         return HPADI_EHIP;
@@ -1360,7 +1505,7 @@ int hpadi_batch_info(hpadi_batch B, int i, int* lines_per_block, int* J, int* st
     if (!B || i < 0 || i >= B->count) return HPADI_EINVAL;
     if (lines_per_block) *lines_per_block = B->lw[i];
     if (J) *J = B->plans[i]->J;
-    if (stream_index) *stream_index = B->stream_of[i];
+    if (stream_index) *stream_index = 0;
     return HPADI_OK;
 }
 

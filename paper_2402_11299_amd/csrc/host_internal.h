@@ -27,7 +27,7 @@ struct DimHost {
     float* tab32 = nullptr;
     int hpad = 0;           // hats padded to a multiple of 8 (internal layout)
     int Npad = 0;           // internal length: hpad + (p-1) n
-    bool uniform = false;   // all elements of equal width and n % 8 == 0 (per-degree coefficient fast path)
+    bool uniform = false;   // all elements of equal width and n % 4 == 0 (per-degree coefficient fast path)
 };
 
 struct hpadi_plan_s {

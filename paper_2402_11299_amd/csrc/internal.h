@@ -112,6 +112,25 @@ int sweep_threads(int n, int lines_per_block);
 // Uniform-mesh fast path (sweep_uni.hip): usable when the mesh is uniform (coef != NULL),
 // n is a multiple of the chains per wavefront and p/2 is one of 4, 8, 16, 32, 64.
 bool sweep_uni_available(const DimDev& d, int lines_per_block);
+// Grouped launches of the uniform-mesh kernel: one launch runs the same half-sweep kind
+// (mode, types, direction, chain length, lines per workgroup) for many problems.
+struct GroupTask {
+    DimDev d;
+    SweepArgs a;
+    int block0;   // first workgroup of this task
+    int nblk;     // its workgroups
+};
+struct GroupLaunch {
+    const GroupTask* tasks;  // device table, sorted by block0
+    int ntasks, nblocks, threads;
+    size_t lds_bytes;
+    int mode, tin, tout, cl, lw;
+    bool column;
+};
+size_t sweep_uni_threads(const DimDev& d, int lw);
+size_t sweep_uni_lds_bytes(const DimDev& d, int lw, int threads, int mode);
+int sweep_uni_max_threads(int cl);
+hipError_t launch_sweep_uni_grouped(const GroupLaunch& g, hipStream_t s);
 hipError_t launch_sweep_uni(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
                             hipStream_t s);
 

@@ -47,7 +47,7 @@ def test_batch_matches_single_solves(hp):
         Us.append(torch.empty_like(G))
         oracles.append((obasis.assemble(obasis.make_basis(nx, px, 0.0, 1.0, bc)),
                         obasis.assemble(obasis.make_basis(ny, py, 0.0, 1.0, bc)), G.cpu().numpy(), w2))
-    batch = hp.Batch(probs, 1e-10, Gs, Us, autotune=True, nstreams=4)
+    batch = hp.Batch(probs, 1e-10, Gs, Us, autotune=True)
     st, extra = batch.solve()
     first = [u.cpu().numpy().copy() for u in Us]
     print(f"  extra FP64 rounds: {extra}; tuned lines per block: {[batch.info(i)[0] for i in range(len(probs))]}",
