@@ -71,20 +71,21 @@ typedef struct {
     double est_rel_err;  /* estimated relative error of U (mixed mode) */
     double res_rel;      /* last FP64 relative residual ||G - A U|| / ||G|| (mixed mode) */
     int fp32_rounds;     /* rounds run with FP32 sweeps (mixed mode) */
-    int reserved0;
+    int J_refine;        /* ADI iterations per FP64 refinement round (mixed mode; J for FP64 plans) */
     double t_ms[3];      /* reserved */
 } hpadi_stats;
 
 /* Options for hpadi_plan_create_ex (zero-initialise, then set fields). */
 typedef struct {
-    double inner_tol;   /* mixed mode: tolerance of the shift family of every round (0 = 3e-6) */
+    double inner_tol;   /* mixed mode: tolerance of the shift family of the FP32 rounds (0 = 3e-7) */
     int max_rounds;     /* mixed mode: refinement round limit (0 = 8) */
     int lines_per_block; /* half-sweep workgroup width: 1, 4 or 8 lines (0 = 4); 1 needs n % 64 == 0 on
                             that axis (else 8); 4 also selects 4-column panels in the internal layout */
     int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
     int fp32_rounds;    /* mixed mode: leading rounds with FP32 sweeps; later rounds are FP64 (0 = 1) */
     int col_lines_per_block; /* column half-sweeps only: 1 or 8 lines (0 = as lines_per_block) */
-    int reserved[2];
+    double refine_tol;  /* mixed mode: tolerance of the shift family of the FP64 refinement rounds
+                           (0 = tol / (4 inner_tol), clamped to [tol, 0.1]) */
 } hpadi_options;
 
 /* ---- 1D operators (Sec. 2, Sec. 3.1, App. A) -------------------------- */

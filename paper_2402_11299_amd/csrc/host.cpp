@@ -501,15 +501,21 @@ int factor_family(DimHost& D, const std::vector<double>& kap, const std::vector<
     return HPADI_OK;
 }
 
+void family_free(ShiftFamily& F) {
+    if (F.facy64 != F.facx64 && F.facx64) hipFree(F.facx64);
+    if (F.facy64) hipFree(F.facy64);
+    if (F.coefy != F.coefx && F.coefx) hipFree(F.coefx);
+    if (F.coefy) hipFree(F.coefy);
+    if (F.ptabx) hipFree(F.ptabx);
+    if (F.ptaby) hipFree(F.ptaby);
+    if (F.status) hipFree(F.status);
+    F = ShiftFamily{};
+}
+
 void plan_free(hpadi_plan_s* P) {
     if (!P) return;
-    if (P->facy64 != P->facx64 && P->facx64) hipFree(P->facx64);
-    if (P->facy64) hipFree(P->facy64);
-    if (P->coefy != P->coefx && P->coefx) hipFree(P->coefx);
-    if (P->coefy) hipFree(P->coefy);
-    if (P->ptabx) hipFree(P->ptabx);
-    if (P->ptaby) hipFree(P->ptaby);
-    for (void* q : {(void*)P->status, P->Wk, P->Gt, (void*)P->T64, (void*)P->T1, (void*)P->T2, (void*)P->R64,
+    for (ShiftFamily& F : P->fam) family_free(F);
+    for (void* q : {P->Wk, P->Gt, (void*)P->T64, (void*)P->T1, (void*)P->T2, (void*)P->R64,
                     (void*)P->H, (void*)P->acc})
         if (q) hipFree(q);
     if (P->acc_host) hipHostFree(P->acc_host);
@@ -529,6 +535,15 @@ hpadi::Layout user_layout(const hpadi_plan_s* P, long ld) {
     L.nhr = P->dx.op.nh;
     L.nhc = P->dy.op.nh;
     return L;
+}
+
+// A row pass reading a panel layout whose rows are narrower than a 128-byte line per
+// workgroup (lines per workgroup x panel width x element size < 128) gets an XCD-aware
+// workgroup order: the workgroups sharing each line run on one XCD.
+hpadi::SweepArgs with_xcd_group(hpadi::SweepArgs a, bool column, int tin) {
+    const int w = a.lpb * a.lin.panel * tin;
+    a.xcd_group = (!column && a.lin.panel > 0 && w > 0 && w < 128) ? 128 / w : 1;
+    return a;
 }
 
 // Launch a half-sweep, bracketed by timing events when measurement is enabled.
@@ -551,56 +566,58 @@ int timed_sweep(hpadi_plan_s* P, bool column, const hpadi::SweepArgs& a, int mod
         if (hipEventRecord(r->a, P->stream) != hipSuccess) return HPADI_EHIP;
     }
     const DimDev& d = column ? P->dx.dev : P->dy.dev;
-    if (hpadi::launch_sweep(d, a, mode, tin, tout, column, P->stream) != hipSuccess) return HPADI_EHIP;
+    if (hpadi::launch_sweep(d, with_xcd_group(a, column, tin), mode, tin, tout, column, P->stream) != hipSuccess)
+        return HPADI_EHIP;
     if (r && hipEventRecord(r->b, P->stream) != hipSuccess) return HPADI_EHIP;
     return HPADI_OK;
 }
 
-// Arguments common to every sweep along one direction; j selects the shifted
-// factor (j = J: the mass factor alone, for the transforms and the final solve).
-hpadi::SweepArgs sweep_args(const hpadi_plan_s* P, bool column, int j) {
+// Arguments common to every sweep along one direction; j selects the shifted factor of
+// family F (j = J: the mass factor alone, for the transforms and the final solve).
+hpadi::SweepArgs sweep_args(const hpadi_plan_s* P, const ShiftFamily& F, bool column, int j) {
     hpadi::SweepArgs a{};
     const DimHost& D = column ? P->dx : P->dy;
     const DimHost& O = column ? P->dy : P->dx;
     const FactorLayout& fl = column ? P->flx : P->fly;
-    const double* fac = column ? P->facx64 : P->facy64;
-    const double* coef = column ? P->coefx : P->coefy;
+    const double* fac = column ? F.facx64 : F.facy64;
+    const double* coef = column ? F.coefx : F.coefy;
     a.nlines = O.op.N;
     a.nh_lines = O.op.nh;
     a.hpad_lines = O.hpad;
     a.fl = fl;
     a.facS = fac + (size_t)j * fl.stride;
-    a.facM = fac + (size_t)P->J * fl.stride;
+    a.facM = fac + (size_t)F.J * fl.stride;
     a.coef = coef ? coef + (size_t)j * D.op.p * 8 : nullptr;
-    const double* ptab = column ? P->ptabx : P->ptaby;
-    a.ptab = ptab ? ptab + (size_t)(j < P->J ? j : 0) * D.op.p * 16 : nullptr;
+    const double* ptab = column ? F.ptabx : F.ptaby;
+    a.ptab = ptab ? ptab + (size_t)(j < F.J ? j : 0) * D.op.p * 16 : nullptr;
     a.lpb = column ? P->lpb_col : P->lpb_row;
     // byte offsets of 8-byte entries must fit the 32-bit offsets of the uniform kernel
     a.idx32 = P->nint < (size_t(1) << 29) ? 1 : 0;
     return a;
 }
 
-// Arguments of the transform passes (column: R -> T64; row: T64 -> G~ in ts bytes).
-hpadi::SweepArgs transform_col_args(const hpadi_plan_s* P, const double* R, long ldr) {
-    hpadi::SweepArgs c = sweep_args(P, true, P->J);
-    c.in = R;
-    c.lin = user_layout(P, ldr);
-    if ((double)ldr * P->dx.op.N >= 536870912.0) c.idx32 = 0;
-    c.out = P->T64;
-    c.lout = P->lint;
-    return c;
-}
-hpadi::SweepArgs transform_row_args(const hpadi_plan_s* P) {
-    hpadi::SweepArgs r = sweep_args(P, false, P->J);
-    r.in = P->T64;
-    r.lin = P->lint;
-    r.out = P->Gt;
+// Arguments of the transform passes (row: R -> T64, reading the caller's row-major R
+// along its rows; column: T64 -> G~ in ts bytes).
+hpadi::SweepArgs transform_row_args(const hpadi_plan_s* P, const double* R, long ldr) {
+    hpadi::SweepArgs r = sweep_args(P, P->first(), false, P->first().J);
+    r.in = R;
+    r.lin = user_layout(P, ldr);
+    if ((double)ldr * P->dx.op.N >= 536870912.0) r.idx32 = 0;
+    r.out = P->T64;
     r.lout = P->lint;
     return r;
 }
+hpadi::SweepArgs transform_col_args(const hpadi_plan_s* P) {
+    hpadi::SweepArgs c = sweep_args(P, P->first(), true, P->first().J);
+    c.in = P->T64;
+    c.lin = P->lint;
+    c.out = P->Gt;
+    c.lout = P->lint;
+    return c;
+}
 // Arguments of the ADI half-sweeps of iteration j (row: shift q_j; column: p_{j+1}).
-hpadi::SweepArgs adi_row_args(const hpadi_plan_s* P, int j) {
-    hpadi::SweepArgs r = sweep_args(P, false, j);
+hpadi::SweepArgs adi_row_args(const hpadi_plan_s* P, const ShiftFamily& F, int j) {
+    hpadi::SweepArgs r = sweep_args(P, F, false, j);
     r.in = j == 0 ? P->Gt : P->Wk;
     r.lin = P->lint;
     r.g = P->Gt;
@@ -608,11 +625,11 @@ hpadi::SweepArgs adi_row_args(const hpadi_plan_s* P, int j) {
     r.out = P->Wk;
     r.lout = P->lint;
     r.kappa = 1.0;
-    r.tau = P->omega2 / 2.0 + P->Q[j];
+    r.tau = P->omega2 / 2.0 + F.Q[j];
     return r;
 }
-hpadi::SweepArgs adi_col_args(const hpadi_plan_s* P, int j) {
-    hpadi::SweepArgs c = sweep_args(P, true, j);
+hpadi::SweepArgs adi_col_args(const hpadi_plan_s* P, const ShiftFamily& F, int j) {
+    hpadi::SweepArgs c = sweep_args(P, F, true, j);
     c.in = P->Wk;
     c.lin = P->lint;
     c.g = P->Gt;
@@ -620,44 +637,46 @@ hpadi::SweepArgs adi_col_args(const hpadi_plan_s* P, int j) {
     c.out = P->Wk;
     c.lout = P->lint;
     c.kappa = 1.0;
-    c.tau = j + 1 == P->J ? 0.0 : P->omega2 / 2.0 - P->P[j + 1];
+    c.tau = j + 1 == F.J ? 0.0 : P->omega2 / 2.0 - F.P[j + 1];
     return c;
 }
-// Arguments of the final mass solve U (+)= L^{-1} w.
-hpadi::SweepArgs final_args(const hpadi_plan_s* P, double* U, long ldu, bool accumulate) {
-    hpadi::SweepArgs f = sweep_args(P, false, P->J);
+// Arguments of the final mass solve U (+)= L^{-1} w; norms: accumulate the weighted
+// squares of the correction and of the new U into P->acc[0..1].
+hpadi::SweepArgs final_args(const hpadi_plan_s* P, double* U, long ldu, bool accumulate, bool norms) {
+    hpadi::SweepArgs f = sweep_args(P, P->first(), false, P->first().J);
     f.in = P->Wk;
     f.lin = P->lint;
     f.out = U;
     f.lout = user_layout(P, ldu);
     if ((double)ldu * P->dx.op.N >= 536870912.0) f.idx32 = 0;
     f.accumulate = accumulate ? 1 : 0;
-    f.norm_acc = accumulate ? P->acc : nullptr;
+    f.norm_acc = norms ? P->acc : nullptr;
     f.wline = P->dx.dev.mdiag;
     return f;
 }
 
-// G~ = V^{-T} R L^{-1}: column then row transform (mass factors M^x = V^T V, M^y = L^T L).
+// G~ = V^{-T} R L^{-1} (mass factors M^x = V^T V, M^y = L^T L): the two sides commute, so
+// the row transform goes first and reads R along its contiguous rows.
 int transform_rhs(hpadi_plan_s* P, const double* R, long ldr, int ts) {
     const double dofs = (double)P->dx.op.N * P->dy.op.N;
-    int rc = timed_sweep(P, true, transform_col_args(P, R, ldr), hpadi::SWEEP_TRANSFORM, 8, 8, 2, dofs * 16.0);
+    int rc = timed_sweep(P, false, transform_row_args(P, R, ldr), hpadi::SWEEP_TRANSFORM, 8, 8, 2, dofs * 16.0);
     if (rc != HPADI_OK) return rc;
-    return timed_sweep(P, false, transform_row_args(P), hpadi::SWEEP_TRANSFORM, 8, ts, 2, dofs * (8.0 + ts));
+    return timed_sweep(P, true, transform_col_args(P), hpadi::SWEEP_TRANSFORM, 8, ts, 2, dofs * (8.0 + ts));
 }
 
-// Alg. 2 solve loop in balanced coordinates, from G~ (in P->Gt) to U (user layout):
-// U = u (FP64 mode) or U += u (refinement rounds).
-int run_adi(hpadi_plan_s* P, int ts, double* U, long ldu, bool accumulate) {
+// Alg. 2 solve loop in balanced coordinates with the shifts of family F, from G~ (in
+// P->Gt) to U (user layout): U = u or U += u (accumulate); norms as in final_args.
+int run_adi(hpadi_plan_s* P, const ShiftFamily& F, int ts, double* U, long ldu, bool accumulate, bool norms) {
     const double dofs = (double)P->dx.op.N * P->dy.op.N;
-    for (int j = 0; j < P->J; ++j) {
-        int rc = timed_sweep(P, false, adi_row_args(P, j), hpadi::SWEEP_FULL, ts, ts, 1, dofs * 3.0 * ts);
+    for (int j = 0; j < F.J; ++j) {
+        int rc = timed_sweep(P, false, adi_row_args(P, F, j), hpadi::SWEEP_FULL, ts, ts, 1, dofs * 3.0 * ts);
         if (rc != HPADI_OK) return rc;
-        const bool last = j + 1 == P->J;
-        rc = timed_sweep(P, true, adi_col_args(P, j), last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts,
+        const bool last = j + 1 == F.J;
+        rc = timed_sweep(P, true, adi_col_args(P, F, j), last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts,
                          last ? 2 : 0, dofs * (last ? 2.0 : 3.0) * ts);
         if (rc != HPADI_OK) return rc;
     }
-    return timed_sweep(P, false, final_args(P, U, ldu, accumulate), hpadi::SWEEP_FINAL, ts, 8, 2,
+    return timed_sweep(P, false, final_args(P, U, ldu, accumulate, norms), hpadi::SWEEP_FINAL, ts, 8, 2,
                        dofs * (ts + (accumulate ? 16.0 : 8.0)));
 }
 
@@ -718,7 +737,6 @@ int residual_into_r64(hpadi_plan_s* P, const double* G, long ldg, const double* 
 // and of U for the error bound.  Work arrays must already exist.
 int enqueue_fixed_solve(hpadi_plan_s* P, const double* G, long ldg, double* U, long ldu, int nfp32, int nfp64) {
     hipStream_t s = P->stream;
-    if (hpadi::launch_zero_f64(U, ldu, P->dx.op.N, P->dy.op.N, s) != hipSuccess) return HPADI_EHIP;
     const int rounds = nfp32 + nfp64;
     for (int k = 1; k <= rounds; ++k) {
         const int ts = k <= nfp32 ? 4 : 8;
@@ -726,7 +744,9 @@ int enqueue_fixed_solve(hpadi_plan_s* P, const double* G, long ldg, double* U, l
         if (k > 1 && (rc = residual_into_r64(P, G, ldg, U, ldu)) != HPADI_OK) return rc;
         if (hpadi::launch_zero_f64(P->acc, 2, 1, 2, s) != hipSuccess) return HPADI_EHIP;
         if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
-        if ((rc = run_adi(P, ts, U, ldu, true)) != HPADI_OK) return rc;
+        // the first round writes U (no zeroing pass), later rounds add to it; FP32 rounds
+        // take the first shift family, FP64 rounds the refinement family
+        if ((rc = run_adi(P, k <= nfp32 ? P->first() : P->refine(), ts, U, ldu, k > 1, true)) != HPADI_OK) return rc;
     }
     return HPADI_OK;
 }
@@ -965,6 +985,71 @@ int hpadi_shifts(const double iv[4], double tol, int J_in, int* J, double* p, do
     return HPADI_OK;
 }
 
+// Shifts (Alg. 2) for tolerance eps and the reverse Cholesky factors (Alg. 1) of the
+// shifted 1D operators of both axes, plus the uniform-mesh coefficient tables.
+int build_family(hpadi_plan_s* P, const hpadi_op1d_s& x, const hpadi_op1d_s& y, double eps, ShiftFamily& F) {
+    int rc;
+    F.eps = eps;
+    if ((rc = compute_shifts(P->interval, eps, 0, &F.J, F.P, F.Q)) != HPADI_OK) return rc;
+    const int J = F.J;
+    if (dmalloc(&F.status, 2 * J + 2) != hipSuccess) return HPADI_ENOMEM;
+    const double half = P->omega2 / 2.0;
+    // y family: K_y + (w/2 + p_j) M_y for j = 1..J, then M_y
+    std::vector<double> ky(J + 1, 1.0), sy(J + 1);
+    for (int j = 0; j < J; ++j) sy[j] = half + F.P[j];
+    ky[J] = 0.0;
+    sy[J] = 1.0;
+    if ((rc = factor_family(P->dy, ky, sy, P->fly, &F.facy64, F.status, P->stream)) != HPADI_OK) return rc;
+    // x family: K_x + (w/2 - q_j) M_x, then M_x; shared with y when operators and shifts coincide
+    bool shared = same_op(x, y);
+    for (int j = 0; j < J && shared; ++j) shared = (-F.Q[j] == F.P[j]);
+    F.shared = shared;
+    if (shared) {
+        F.facx64 = F.facy64;
+        P->flx = P->fly;
+    } else {
+        std::vector<double> kx(J + 1, 1.0), sx(J + 1);
+        for (int j = 0; j < J; ++j) sx[j] = half - F.Q[j];
+        kx[J] = 0.0;
+        sx[J] = 1.0;
+        if ((rc = factor_family(P->dx, kx, sx, P->flx, &F.facx64, F.status + J + 1, P->stream)) != HPADI_OK) return rc;
+    }
+    // per-degree coefficient records for the uniform-mesh fast path
+    auto tables = [&](DimHost& D, double* fac, const FactorLayout& fl, double** out) -> int {
+        if (!D.uniform || D.op.p < 2) return HPADI_OK;
+        if (dmalloc(out, (size_t)(J + 1) * D.op.p * 8) != hipSuccess) return HPADI_ENOMEM;
+        return hpadi::launch_coef_tables(D.dev, J + 1, fac, fl.stride, fac + (size_t)J * fl.stride, fl, *out,
+                                         P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
+    };
+    if ((rc = tables(P->dy, F.facy64, P->fly, &F.coefy)) != HPADI_OK) return rc;
+    if (shared) F.coefx = F.coefy;
+    else if ((rc = tables(P->dx, F.facx64, P->flx, &F.coefx)) != HPADI_OK) return rc;
+    // folded per-pass records: row pass j (S_y(w/2 + p_j), product tau = w/2 + q_j) and
+    // column pass j (S_x(w/2 - q_j), product tau = w/2 - p_{j+1}; none after the last)
+    auto ptables = [&](DimHost& D, double* fac, const FactorLayout& fl, const std::vector<double>& tau,
+                       double** out) -> int {
+        if (!D.uniform || D.op.p < 2) return HPADI_OK;
+        if (dmalloc(out, (size_t)J * D.op.p * 16) != hipSuccess) return HPADI_ENOMEM;
+        double* td = nullptr;
+        if (dmalloc(&td, J) != hipSuccess) return HPADI_ENOMEM;
+        int r = HPADI_OK;
+        if (hipMemcpyAsync(td, tau.data(), J * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+            hpadi::launch_pass_tables(D.dev, J, fac, fl.stride, fac + (size_t)J * fl.stride, fl, td, 1.0, *out,
+                                      P->stream) != hipSuccess ||
+            hipStreamSynchronize(P->stream) != hipSuccess)
+            r = HPADI_EHIP;
+        hipFree(td);
+        return r;
+    };
+    std::vector<double> tr(J), tc(J);
+    for (int j = 0; j < J; ++j) {
+        tr[j] = half + F.Q[j];
+        tc[j] = j + 1 < J ? half - F.P[j + 1] : 0.0;
+    }
+    if ((rc = ptables(P->dy, F.facy64, P->fly, tr, &F.ptaby)) != HPADI_OK) return rc;
+    return ptables(P->dx, F.facx64, P->flx, tc, &F.ptabx);
+}
+
 int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,
                          const double* interval, void* hip_stream, const hpadi_options* opts, hpadi_plan* out) {
     if (!out) return HPADI_EINVAL;
@@ -978,7 +1063,7 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     hpadi_plan_s* P = new (std::nothrow) hpadi_plan_s;
     if (!P) return HPADI_ENOMEM;
     if (opts) P->opt = *opts;
-    if (!(P->opt.inner_tol > 0.0)) P->opt.inner_tol = 3e-6;
+    if (!(P->opt.inner_tol > 0.0)) P->opt.inner_tol = 3e-7;
     if (P->opt.fp32_rounds <= 0) P->opt.fp32_rounds = 1;
     if (P->opt.max_rounds <= 0) P->opt.max_rounds = 8;
     P->omega2 = omega2;
@@ -999,76 +1084,20 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
         P->interval[2] = -iy[1];
         P->interval[3] = -iy[0];
     }
-    const double adi_tol = precision == HPADI_FP64 ? tol : std::max(P->opt.inner_tol, tol);
-    P->adi_eps = adi_tol;
-    if ((rc = compute_shifts(P->interval, adi_tol, 0, &P->J, P->P, P->Q)) != HPADI_OK) { plan_free(P); return rc; }
     if ((rc = make_dim(P->dx, *x)) != HPADI_OK || (rc = make_dim(P->dy, *y)) != HPADI_OK) { plan_free(P); return rc; }
-    const int J = P->J;
-    if (dmalloc(&P->status, 2 * J + 2) != hipSuccess) { plan_free(P); return HPADI_ENOMEM; }
-    const double half = omega2 / 2.0;
-    // y family: K_y + (w/2 + p_j) M_y for j = 1..J, then M_y
-    std::vector<double> ky(J + 1, 1.0), sy(J + 1);
-    for (int j = 0; j < J; ++j) sy[j] = half + P->P[j];
-    ky[J] = 0.0;
-    sy[J] = 1.0;
-    if ((rc = factor_family(P->dy, ky, sy, P->fly, &P->facy64, P->status, P->stream)) != HPADI_OK) {
-        plan_free(P);
-        return rc;
-    }
-    // x family: K_x + (w/2 - q_j) M_x, then M_x; shared with y when operators and shifts coincide
-    bool shared = same_op(*x, *y);
-    for (int j = 0; j < J && shared; ++j) shared = (-P->Q[j] == P->P[j]);
-    P->shared = shared;
-    if (shared) {
-        P->facx64 = P->facy64;
-        P->flx = P->fly;
-    } else {
-        std::vector<double> kx(J + 1, 1.0), sx(J + 1);
-        for (int j = 0; j < J; ++j) sx[j] = half - P->Q[j];
-        kx[J] = 0.0;
-        sx[J] = 1.0;
-        if ((rc = factor_family(P->dx, kx, sx, P->flx, &P->facx64, P->status + J + 1, P->stream)) != HPADI_OK) {
-            plan_free(P);
-            return rc;
-        }
-    }
-    // per-degree coefficient records for the uniform-mesh fast path
-    auto tables = [&](DimHost& D, double* fac, const FactorLayout& fl, double** out) -> int {
-        if (!D.uniform || D.op.p < 2) return HPADI_OK;
-        if (dmalloc(out, (size_t)(J + 1) * D.op.p * 8) != hipSuccess) return HPADI_ENOMEM;
-        return hpadi::launch_coef_tables(D.dev, J + 1, fac, fl.stride, fac + (size_t)J * fl.stride, fl, *out,
-                                         P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
-    };
-    if ((rc = tables(P->dy, P->facy64, P->fly, &P->coefy)) != HPADI_OK) { plan_free(P); return rc; }
-    if (shared) P->coefx = P->coefy;
-    else if ((rc = tables(P->dx, P->facx64, P->flx, &P->coefx)) != HPADI_OK) { plan_free(P); return rc; }
-    // folded per-pass records: row pass j (S_y(w/2 + p_j), product tau = w/2 + q_j) and
-    // column pass j (S_x(w/2 - q_j), product tau = w/2 - p_{j+1}; none after the last)
-    auto ptables = [&](DimHost& D, double* fac, const FactorLayout& fl, const std::vector<double>& tau,
-                       double** out) -> int {
-        if (!D.uniform || D.op.p < 2) return HPADI_OK;
-        if (dmalloc(out, (size_t)J * D.op.p * 16) != hipSuccess) return HPADI_ENOMEM;
-        double* td = nullptr;
-        if (dmalloc(&td, J) != hipSuccess) return HPADI_ENOMEM;
-        int r = HPADI_OK;
-        if (hipMemcpyAsync(td, tau.data(), J * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
-            hpadi::launch_pass_tables(D.dev, J, fac, fl.stride, fac + (size_t)J * fl.stride, fl, td, 1.0, *out,
-                                      P->stream) != hipSuccess ||
-            hipStreamSynchronize(P->stream) != hipSuccess)
-            r = HPADI_EHIP;
-        hipFree(td);
-        return r;
-    };
-    {
-        std::vector<double> tr(J), tc(J);
-        for (int j = 0; j < J; ++j) {
-            tr[j] = half + P->Q[j];
-            tc[j] = j + 1 < J ? half - P->P[j + 1] : 0.0;
-        }
-        if ((rc = ptables(P->dy, P->facy64, P->fly, tr, &P->ptaby)) != HPADI_OK ||
-            (rc = ptables(P->dx, P->facx64, P->flx, tc, &P->ptabx)) != HPADI_OK) {
-            plan_free(P);
-            return rc;
+    // FP64 plans: one family for tol.  Mixed plans: the FP32 rounds use inner_tol; the
+    // FP64 refinement rounds need only tol / (2 e), with e the error left by the FP32
+    // round, which follows inner_tol down to the FP32 rounding floor: a family for
+    // tol / (4 inner_tol) allows e up to twice inner_tol, and a further FP64 round
+    // covers a larger one.
+    const double eps0 = precision == HPADI_FP64 ? tol : std::max(P->opt.inner_tol, tol);
+    if ((rc = build_family(P, *x, *y, eps0, P->fam[0])) != HPADI_OK) { plan_free(P); return rc; }
+    if (precision == HPADI_MIXED) {
+        double eps1 = P->opt.refine_tol > 0.0 ? P->opt.refine_tol : tol / (4.0 * eps0);
+        eps1 = std::min(0.1, std::max(eps1, tol));
+        if (eps1 != eps0) {
+            if ((rc = build_family(P, *x, *y, eps1, P->fam[1])) != HPADI_OK) { plan_free(P); return rc; }
+            P->nfam = 2;
         }
     }
     // workspace: internal panel layout (8-column panels, hats padded to a multiple of 8)
@@ -1114,10 +1143,11 @@ int hpadi_plan_create(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int
 
 int hpadi_plan_info(hpadi_plan P, int* J, double* p, double* q, double interval[4]) {
     if (!P) return HPADI_EINVAL;
-    if (J) *J = P->J;
-    for (int j = 0; j < P->J; ++j) {
-        if (p) p[j] = P->P[j];
-        if (q) q[j] = P->Q[j];
+    const ShiftFamily& F = P->first();
+    if (J) *J = F.J;
+    for (int j = 0; j < F.J; ++j) {
+        if (p) p[j] = F.P[j];
+        if (q) q[j] = F.Q[j];
     }
     if (interval)
         for (int i = 0; i < 4; ++i) interval[i] = P->interval[i];
@@ -1127,10 +1157,11 @@ int hpadi_plan_info(hpadi_plan P, int* J, double* p, double* q, double interval[
 int hpadi_plan_export_factor(hpadi_plan P, int j, int axis, double* buf, size_t len) {
     if (!P || !buf || (axis != 0 && axis != 1)) return HPADI_EINVAL;
     const FactorLayout& fl = axis == 0 ? P->flx : P->fly;
-    const double* base = axis == 0 ? P->facx64 : P->facy64;
-    const int idx = j == -1 ? P->J : j;
+    const ShiftFamily& F = P->first();
+    const double* base = axis == 0 ? F.facx64 : F.facy64;
+    const int idx = j == -1 ? F.J : j;
     const size_t doc = (size_t)fl.off_link0 + (fl.off_link0 - fl.off_invd0);  // documented prefix
-    if (idx < 0 || idx > P->J || len < doc) return HPADI_EINVAL;
+    if (idx < 0 || idx > F.J || len < doc) return HPADI_EINVAL;
     if (hipMemcpyAsync(buf, base + (size_t)idx * fl.stride, doc * sizeof(double), hipMemcpyDeviceToHost,
                        P->stream) != hipSuccess ||
         hipStreamSynchronize(P->stream) != hipSuccess)
@@ -1172,16 +1203,17 @@ int hpadi_apply(hpadi_plan P, const double* U, int ldu, double* Y, int ldy) {
 int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpadi_stats* stats) {
     if (!P || !G || !U || ldg < P->dy.op.N || ldu < P->dy.op.N) return HPADI_EINVAL;
     hpadi_stats st{};
-    st.J = P->J;
+    st.J = P->first().J;
+    st.J_refine = P->refine().J;
     for (int i = 0; i < 4; ++i) st.interval[i] = P->interval[i];
     hipStream_t s = P->stream;
     const int Nx = P->dx.op.N, Ny = P->dy.op.N;
     int rc = HPADI_OK;
     if (P->precision == HPADI_FP64) {
         if ((rc = transform_rhs(P, G, ldg, 8)) != HPADI_OK) return rc;
-        if ((rc = run_adi(P, 8, U, ldu, false)) != HPADI_OK) return rc;
+        if ((rc = run_adi(P, P->first(), 8, U, ldu, false, false)) != HPADI_OK) return rc;
         st.rounds = 1;
-        st.iters = P->J;
+        st.iters = P->first().J;
         st.est_rel_err = P->tol;
     } else {
         // Iterative refinement: U = 0; repeat { delta = ADI(r); U += delta; r = G - A U (FP64) }.
@@ -1189,14 +1221,13 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
         // FP64, where the ADI lemma bounds the error of the round: with e the error before
         // the round and delta its correction, ||e - delta|| <= eps ||e|| and ||e|| <= ||delta||
         // / (1 - eps), so ||U* - U|| <= eps / (1 - eps) ||delta|| (eps: tolerance of the
-        // shift family).  Norms are diagonal-mass weighted; kNormSafety covers the ratio of
-        // that norm to the L2 norm.  FP32 rounds have no such bound (their rounding floor
-        // depends on the spectrum of the residual) and never end the solve.
+        // shift family of the round).  Norms are diagonal-mass weighted; kNormSafety covers
+        // the ratio of that norm to the L2 norm.  FP32 rounds have no such bound (their
+        // rounding floor depends on the spectrum of the residual) and never end the solve.
+        // FP32 rounds take the first shift family, FP64 rounds the refinement family.
         if ((rc = ensure_fp64_work(P)) != HPADI_OK) return rc;
         if (!P->R64 && dmalloc(&P->R64, (size_t)Nx * P->ldw) != hipSuccess) return HPADI_ENOMEM;
-        if (hpadi::launch_zero_f64(U, ldu, Nx, Ny, s) != hipSuccess) return HPADI_EHIP;
         constexpr double kNormSafety = 2.0;
-        const double eps = P->adi_eps;
         double est = 1.0;
         const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
         int k = 0;
@@ -1204,10 +1235,13 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
         for (k = 1; k <= maxr; ++k) {
             const bool fp32 = k <= P->opt.fp32_rounds;
             const int ts = fp32 ? 4 : 8;
+            const ShiftFamily& F = fp32 ? P->first() : P->refine();
+            const double eps = F.eps;
             if (hipMemsetAsync(P->acc, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
             if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
-            if ((rc = run_adi(P, ts, U, ldu, true)) != HPADI_OK) return rc;
-            st.iters += P->J;
+            // the first round writes U, later rounds add their correction to it
+            if ((rc = run_adi(P, F, ts, U, ldu, k > 1, true)) != HPADI_OK) return rc;
+            st.iters += F.J;
             if (fp32) st.fp32_rounds++;
             const bool decide = P->opt.fixed_rounds <= 0 && !fp32;
             if (decide || k == maxr) {
@@ -1294,6 +1328,11 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     auto make_plan = [&](int i, int lw, hpadi_plan* pl) -> int {
         hpadi_options o{};
         o.lines_per_block = lw;
+        // one family (3e-6) for both rounds: the batch's small, rough instances leave FP32
+        // errors well above 3e-7, so a looser FP64 family would send many of them to a
+        // further round outside the graph
+        o.inner_tol = 3e-6;
+        o.refine_tol = 3e-6;
         int rc = hpadi_plan_create_ex(xs[i], ys[i], omega2[i], tol, HPADI_MIXED, nullptr, B->origin, &o, pl);
         if (rc != HPADI_OK) return rc;
         hpadi_plan_s* P = *pl;
@@ -1367,41 +1406,48 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     // of one iteration as few grouped launches as there are (chain length, width) pairs
     std::vector<BatchStep> steps;
     std::vector<hpadi::GroupTask> table;
-    int jmax = 0;
-    for (int i = 0; i < count; ++i) jmax = std::max(jmax, B->plans[i]->J);
     for (int round = 1; round <= 2; ++round) {
         const int ts = round == 1 ? 4 : 8;
+        // round 1: FP32 sweeps with the first shift family; round 2: FP64 sweeps with the
+        // refinement family
+        auto fam = [&](const hpadi_plan_s* P) -> const ShiftFamily& { return round == 1 ? P->first() : P->refine(); };
+        int jmax = 0;
+        for (int i = 0; i < count; ++i) jmax = std::max(jmax, fam(B->plans[i]).J);
         for (int i = 0; i < count; ++i) {
+            // round 1 writes U (no zeroing pass); round 2 starts from the FP64 residual
             BatchStep st;
             st.inst = i;
-            st.kind = round == 1 ? 3 : 2;
-            steps.push_back(st);
+            if (round == 2) {
+                st.kind = 2;
+                steps.push_back(st);
+            }
             st.kind = 4;
             steps.push_back(st);
         }
         std::vector<std::pair<int, hpadi::SweepArgs>> items;
         for (int i = 0; i < count; ++i) {
             hpadi_plan_s* P = B->plans[i];
-            items.push_back({i, transform_col_args(P, round == 1 ? G[i] : P->R64, round == 1 ? ldg[i] : P->ldw)});
+            items.push_back({i, transform_row_args(P, round == 1 ? G[i] : P->R64, round == 1 ? ldg[i] : P->ldw)});
         }
-        add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, 8, true);
+        add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, 8, false);
         items.clear();
-        for (int i = 0; i < count; ++i) items.push_back({i, transform_row_args(B->plans[i])});
-        add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, ts, false);
+        for (int i = 0; i < count; ++i) items.push_back({i, transform_col_args(B->plans[i])});
+        add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, ts, true);
         for (int jj = 0; jj < jmax; ++jj) {
             std::vector<std::pair<int, hpadi::SweepArgs>> rows, cols, last;
             for (int i = 0; i < count; ++i) {
                 hpadi_plan_s* P = B->plans[i];
-                if (jj >= P->J) continue;
-                rows.push_back({i, adi_row_args(P, jj)});
-                (jj + 1 == P->J ? last : cols).push_back({i, adi_col_args(P, jj)});
+                const ShiftFamily& F = fam(P);
+                if (jj >= F.J) continue;
+                rows.push_back({i, adi_row_args(P, F, jj)});
+                (jj + 1 == F.J ? last : cols).push_back({i, adi_col_args(P, F, jj)});
             }
             add_sweeps(steps, table, B->plans, rows, hpadi::SWEEP_FULL, ts, ts, false);
             add_sweeps(steps, table, B->plans, cols, hpadi::SWEEP_FULL, ts, ts, true);
             add_sweeps(steps, table, B->plans, last, hpadi::SWEEP_SOLVE, ts, ts, true);
         }
         items.clear();
-        for (int i = 0; i < count; ++i) items.push_back({i, final_args(B->plans[i], U[i], ldu[i], true)});
+        for (int i = 0; i < count; ++i) items.push_back({i, final_args(B->plans[i], U[i], ldu[i], round > 1, true)});
         add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_FINAL, ts, 8, false);
     }
     if (!table.empty() &&
@@ -1464,7 +1510,7 @@ int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
     int extra = 0, status = HPADI_OK;
     for (int i = 0; i < B->count; ++i) {
         hpadi_plan_s* P = B->plans[i];
-        const double eps = P->adi_eps;
+        const double eps = P->refine().eps;
         double nd = std::sqrt(std::max(B->acc_host[2 * i], 0.0)), nu = std::sqrt(std::max(B->acc_host[2 * i + 1], 0.0));
         double est = nu > 0 ? kNormSafety * eps / (1.0 - eps) * nd / nu : 0.0;
         int rounds = 2;
@@ -1472,7 +1518,7 @@ int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
             int rc = residual_into_r64(P, B->G[i], B->ldg[i], B->U[i], B->ldu[i]);
             if (rc == HPADI_OK && hpadi::launch_zero_f64(P->acc, 2, 1, 2, P->stream) != hipSuccess) rc = HPADI_EHIP;
             if (rc == HPADI_OK) rc = transform_rhs(P, P->R64, P->ldw, 8);
-            if (rc == HPADI_OK) rc = run_adi(P, 8, B->U[i], B->ldu[i], true);
+            if (rc == HPADI_OK) rc = run_adi(P, P->refine(), 8, B->U[i], B->ldu[i], true, true);
             if (rc == HPADI_OK &&
                 (hipMemcpyAsync(P->acc_host, P->acc, 2 * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
                  hipStreamSynchronize(P->stream) != hipSuccess))
@@ -1487,10 +1533,11 @@ int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
         if (!(est <= B->tol)) status = HPADI_ENOCONV;
         if (stats) {
             hpadi_stats st{};
-            st.J = P->J;
+            st.J = P->first().J;
+            st.J_refine = P->refine().J;
             st.rounds = rounds;
             st.fp32_rounds = 1;
-            st.iters = rounds * P->J;
+            st.iters = P->first().J + (rounds - 1) * P->refine().J;
             st.status = est <= B->tol ? HPADI_OK : HPADI_ENOCONV;
             st.est_rel_err = est;
             for (int k = 0; k < 4; ++k) st.interval[k] = P->interval[k];
@@ -1504,7 +1551,7 @@ int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
 int hpadi_batch_info(hpadi_batch B, int i, int* lines_per_block, int* J, int* stream_index) {
     if (!B || i < 0 || i >= B->count) return HPADI_EINVAL;
     if (lines_per_block) *lines_per_block = B->lw[i];
-    if (J) *J = B->plans[i]->J;
+    if (J) *J = B->plans[i]->first().J;
     if (stream_index) *stream_index = 0;
     return HPADI_OK;
 }

@@ -30,19 +30,13 @@ struct DimHost {
     bool uniform = false;   // all elements of equal width and n % 4 == 0 (per-degree coefficient fast path)
 };
 
-struct hpadi_plan_s {
-    DimHost dx, dy;
-    double omega2 = 0.0, tol = 0.0;
-    int precision = HPADI_FP64;
-    hpadi_options opt{};
-    double interval[4] = {0, 0, 0, 0};
+// One shift family of Alg. 2: the J shift pairs for a tolerance and the reverse
+// Cholesky factors of the shifted 1D operators (plus the mass matrices) on the device.
+struct ShiftFamily {
     int J = 0;
-    double adi_eps = 0.0;         // tolerance the shift family was built for
-    int lpb_col = 8, lpb_row = 8; // lines per workgroup of the column / row half-sweeps
+    double eps = 0.0;             // tolerance the shifts were built for
     std::vector<double> P, Q;
-    hipStream_t stream = nullptr;
     bool shared = false;          // x and y use one factor family
-    hpadi::FactorLayout flx{}, fly{};
     double* facx64 = nullptr;     // J+1 records: K_x + (w/2 - q_j) M_x, then M_x
     double* facy64 = nullptr;     // J+1 records: K_y + (w/2 + p_j) M_y, then M_y
     double* coefx = nullptr;      // uniform meshes: (J+1) (p_x-1) 8 per-degree coefficient records
@@ -50,6 +44,23 @@ struct hpadi_plan_s {
     double* ptabx = nullptr;      // uniform meshes: J folded per-pass tables (p_x records of 16 doubles)
     double* ptaby = nullptr;
     int* status = nullptr;
+};
+
+struct hpadi_plan_s {
+    DimHost dx, dy;
+    double omega2 = 0.0, tol = 0.0;
+    int precision = HPADI_FP64;
+    hpadi_options opt{};
+    double interval[4] = {0, 0, 0, 0};
+    // fam[0]: the family of an FP64 plan, or of the FP32 rounds of a mixed plan;
+    // fam[nfam - 1]: the family of the FP64 refinement rounds of a mixed plan
+    ShiftFamily fam[2];
+    int nfam = 1;
+    int lpb_col = 8, lpb_row = 8; // lines per workgroup of the column / row half-sweeps
+    hipStream_t stream = nullptr;
+    hpadi::FactorLayout flx{}, fly{};
+    const ShiftFamily& first() const { return fam[0]; }
+    const ShiftFamily& refine() const { return fam[nfam - 1]; }
     // work arrays in the internal panel layout
     hpadi::Layout lint{};
     size_t nint = 0;              // elements per internal array

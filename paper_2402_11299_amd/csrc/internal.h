@@ -85,6 +85,7 @@ struct SweepArgs {
     int accumulate;                 // FINAL: U += u (1) or U = u (0)
     int lpb;                        // lines per workgroup: the panel width of the internal layout (4 or 8)
     int idx32;                      // every array addressed by this sweep has < 2^31 entries
+    int xcd_group;                  // row passes: workgroups sharing 128-byte lines (1 = none)
     double* norm_acc;               // FINAL: [sum w u^2, sum w U^2] or NULL
     const double* wline;            // FINAL: weight per line
 };

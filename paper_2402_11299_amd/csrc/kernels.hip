@@ -214,24 +214,45 @@ __global__ void __launch_bounds__(256) op_apply_cols(DimDev d, OpApply a) {
 
 // r[i][j] = alpha G[i][j] + beta ((ax_k K + ax_t M) T1 + M T2)[i][j], operators along x.
 __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
-    // A block owns 256 columns and the rows blockIdx.y, blockIdx.y + gridDim.y, ...;
-    // the weighted sums of squares are reduced per block (one atomic pair per block).
+    // A block owns 256 columns and a contiguous band of rows; a thread takes RU rows at a
+    // time and issues all their loads before any store (the stores may not be reordered
+    // above loads through possibly aliasing pointers), so RU rows of gathers are in
+    // flight at once.  The weighted sums of squares are reduced per block (one atomic
+    // pair per block).
+    constexpr int RU = 4;
     __shared__ double red[2][4];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rpb = (dx.N + gridDim.y - 1) / gridDim.y;
+    const int ibeg = blockIdx.y * rpb, iend = min(dx.N, ibeg + rpb);
     double sr = 0.0, sg = 0.0;
     if (j < a.ncols) {
-        for (int i = blockIdx.y; i < dx.N; i += gridDim.y) {
-            double K1, M1, K2, M2;
-            gather_km(dx, a.T1 + j, a.t_ld, i, K1, M1);
-            gather_km(dx, a.T2 + j, a.t_ld, i, K2, M2);
-            const double g = a.G ? a.G[(long)i * a.g_ld + j] : 0.0;
-            const double r = a.alpha * g + a.beta * (a.ax_k * K1 + a.ax_t * M1 + M2);
-            if (a.r64) a.r64[(long)i * a.r64_ld + j] = r;
-            if (a.r32) a.r32[(long)i * a.r32_ld + j] = (float)r;
-            if (a.norm_acc) {
-                const double w = dx.mdiag[i] * a.wcol[j];
-                sr += w * r * r;
-                sg += w * g * g;
+        for (int i0 = ibeg; i0 < iend; i0 += RU) {
+            double rv[RU], gv[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int i = i0 + u;
+                rv[u] = 0.0;
+                gv[u] = 0.0;
+                if (i < iend) {
+                    double K1, M1, K2, M2;
+                    gather_km(dx, a.T1 + j, a.t_ld, i, K1, M1);
+                    gather_km(dx, a.T2 + j, a.t_ld, i, K2, M2);
+                    gv[u] = a.G ? a.G[(long)i * a.g_ld + j] : 0.0;
+                    rv[u] = a.alpha * gv[u] + a.beta * (a.ax_k * K1 + a.ax_t * M1 + M2);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int i = i0 + u;
+                if (i >= iend) continue;
+                const double r = rv[u], g = gv[u];
+                if (a.r64) a.r64[(long)i * a.r64_ld + j] = r;
+                if (a.r32) a.r32[(long)i * a.r32_ld + j] = (float)r;
+                if (a.norm_acc) {
+                    const double w = dx.mdiag[i] * a.wcol[j];
+                    sr += w * r * r;
+                    sg += w * g * g;
+                }
             }
         }
     }

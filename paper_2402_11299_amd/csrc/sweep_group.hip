@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_grouped_kerne
         if (t[mid].block0 <= b) lo = mid;
         else hi = mid - 1;
     }
-    sweep_uni_body<TIN, TOUT, CL, MODE, COL, LW>(t[lo].d, t[lo].a, b - t[lo].block0, t[lo].nblk);
+    sweep_uni_body<TIN, TOUT, CL, MODE, COL, LW>(t[lo].d, t[lo].a, b - t[lo].block0, t[lo].nblk, false);
 }
 
 template <typename TIN, typename TOUT, int CL, int MODE, bool COL, int LW>

@@ -16,7 +16,7 @@ namespace {
 
 template <typename TIN, typename TOUT, int CL, int MODE, bool COL, int LW>
 __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_uni_kernel(DimDev d, SweepArgs a) {
-    sweep_uni_body<TIN, TOUT, CL, MODE, COL, LW>(d, a, blockIdx.x, gridDim.x);
+    sweep_uni_body<TIN, TOUT, CL, MODE, COL, LW>(d, a, blockIdx.x, gridDim.x, true);
 }
 
 template <typename TIN, typename TOUT, int CL, int MODE, bool COL, int LW>

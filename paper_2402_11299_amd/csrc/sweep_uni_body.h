@@ -28,8 +28,11 @@ typedef const __attribute__((address_space(4))) double* cptr;
 
 // The half-sweep of workgroup bid (of nblk) of one problem; d and a may live in kernel
 // arguments or in a device task table (grouped launches).
+// standalone: the workgroup index is the hardware one (workgroup b runs on XCD b mod 8),
+// so the line-to-workgroup mapping may be made XCD-aware.
 template <typename TIN, typename TOUT, int CL, int MODE, bool COL, int LW>
-__device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs& a, int bid, int nblk) {
+__device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs& a, int bid, int nblk,
+                                               bool standalone) {
     constexpr int CW = 64 / LW;
     extern __shared__ double sm[];
     const int n = d.n, p = d.p, nh = d.nh;
@@ -85,7 +88,19 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     // 32-byte sector, so their workgroups are placed on one XCD (workgroup b runs on
     // XCD b mod 8) in consecutive dispatch slots, where they share that XCD's L2.
     int blk = bid;
-    if (LW == 1 && COL) {
+    if (standalone && !COL && a.xcd_group > 1) {
+        // A row pass whose workgroup covers only part of each 128-byte line of a panel
+        // (4 rows of 16 bytes in FP32): the xcd_group workgroups sharing those lines run
+        // on one XCD in consecutive dispatch slots, so the line is fetched into that
+        // XCD's L2 once instead of once per XCD.
+        const int g = a.xcd_group;
+        const int full = (nblk / (8 * g)) * (8 * g);
+        if (blk < full) {
+            const int xcd = blk % 8, slot = blk / 8;
+            blk = (slot / g) * (8 * g) + xcd * g + slot % g;
+        }
+    }
+    if (standalone && LW == 1 && COL) {
         const int full = (nblk / 64) * 64;
         if (blk < full) {
             const int xcd = blk % 8, slot = blk / 8;

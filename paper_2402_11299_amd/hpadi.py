@@ -26,14 +26,14 @@ class hpadi_stats(ctypes.Structure):
     _fields_ = [("J", ctypes.c_int), ("rounds", ctypes.c_int), ("iters", ctypes.c_int),
                 ("status", ctypes.c_int), ("interval", ctypes.c_double * 4),
                 ("est_rel_err", ctypes.c_double), ("res_rel", ctypes.c_double),
-                ("fp32_rounds", ctypes.c_int), ("reserved0", ctypes.c_int), ("t_ms", ctypes.c_double * 3)]
+                ("fp32_rounds", ctypes.c_int), ("J_refine", ctypes.c_int), ("t_ms", ctypes.c_double * 3)]
 
 
 class hpadi_options(ctypes.Structure):
     _fields_ = [("inner_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
                 ("lines_per_block", ctypes.c_int),
                 ("fixed_rounds", ctypes.c_int), ("fp32_rounds", ctypes.c_int),
-                ("col_lines_per_block", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("col_lines_per_block", ctypes.c_int), ("refine_tol", ctypes.c_double)]
 
 
 class hpadi_krylov_stats(ctypes.Structure):
