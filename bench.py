@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--only-mixed", action="store_true", help="time only the headline solve (profiling)")
+    ap.add_argument("--only-batch", action="store_true", help="run only the 512-instance batch (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -292,6 +293,9 @@ def main():
     from paper_2402_11299_amd import hpadi as hp
     hp.lib()
     torch.cuda.init()
+    if args.only_batch:
+        print(json.dumps(batch_solve(hp, torch, steps=args.steps)), flush=True)
+        return
     cfgD = workloads.CFG_MIXED_4K_D
     cfgN = workloads.CFG_MIXED_4K_N
 

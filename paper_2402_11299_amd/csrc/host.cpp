@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -14,6 +15,10 @@
 
 #include "internal.h"
 #include "host_internal.h"
+
+// The Python binding mirrors these structs with ctypes; their layout is part of the ABI.
+static_assert(sizeof(hpadi_options) == 40 && offsetof(hpadi_options, refine_tol) == 32, "hpadi_options layout");
+static_assert(sizeof(hpadi_stats) == 96 && offsetof(hpadi_stats, J_refine) == 68, "hpadi_stats layout");
 
 using hpadi::DimDev;
 using hpadi::FactorLayout;
@@ -757,7 +762,8 @@ namespace {
 
 // One launch of a batch schedule.
 struct BatchStep {
-    int kind = 0;        // 0 grouped sweep, 1 single sweep, 2 residual, 3 zero U, 4 zero accumulators
+    int kind = 0;        // 0 grouped sweep, 1 single sweep, 2 residual of one instance, 4 zero all accumulators
+    int phase = 0;       // steps of one phase touch disjoint instances and may run concurrently
     hpadi::GroupLaunch g{};
     size_t task_off = 0;
     int inst = -1;
@@ -852,6 +858,11 @@ struct hpadi_batch_s {
     bool own_origin = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // capture lanes besides the origin stream (default priority): the steps of one phase
+    // are spread over them, forked from and joined back into the origin stream
+    static constexpr int kLanes = 4;
+    hipStream_t side[kLanes - 1] = {};
+    hipEvent_t fork = nullptr, join[kLanes - 1] = {};
     hpadi::GroupTask* table = nullptr;   // device task tables of the grouped launches
     int nlaunch = 0;                     // launches in the graph
     double tol = 0.0;
@@ -864,6 +875,11 @@ struct hpadi_batch_s {
         if (graph) (void)hipGraphDestroy(graph);
         for (hpadi_plan p : plans) hpadi_plan_destroy(p);
         if (own_origin) (void)hipStreamDestroy(origin);
+        for (hipStream_t q : side)
+            if (q) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : join)
+            if (e) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
         (void)hipFree(acc_ptrs);
         (void)hipFree(acc_all);
         (void)hipFree(table);
@@ -1406,6 +1422,14 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     // of one iteration as few grouped launches as there are (chain length, width) pairs
     std::vector<BatchStep> steps;
     std::vector<hpadi::GroupTask> table;
+    // phases: the steps appended since the last seal touch disjoint instances
+    int nphase = 0;
+    size_t mark = 0;
+    auto seal = [&]() {
+        for (size_t k = mark; k < steps.size(); ++k) steps[k].phase = nphase;
+        ++nphase;
+        mark = steps.size();
+    };
     for (int round = 1; round <= 2; ++round) {
         const int ts = round == 1 ? 4 : 8;
         // round 1: FP32 sweeps with the first shift family; round 2: FP64 sweeps with the
@@ -1413,26 +1437,32 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         auto fam = [&](const hpadi_plan_s* P) -> const ShiftFamily& { return round == 1 ? P->first() : P->refine(); };
         int jmax = 0;
         for (int i = 0; i < count; ++i) jmax = std::max(jmax, fam(B->plans[i]).J);
-        for (int i = 0; i < count; ++i) {
-            // round 1 writes U (no zeroing pass); round 2 starts from the FP64 residual
-            BatchStep st;
-            st.inst = i;
-            if (round == 2) {
+        // round 1 writes U (no zeroing pass); round 2 starts from the FP64 residual of every
+        // instance; one launch clears the correction norms of all instances
+        if (round == 2)
+            for (int i = 0; i < count; ++i) {
+                BatchStep st;
                 st.kind = 2;
+                st.inst = i;
                 steps.push_back(st);
             }
+        {
+            BatchStep st;
             st.kind = 4;
             steps.push_back(st);
         }
+        seal();
         std::vector<std::pair<int, hpadi::SweepArgs>> items;
         for (int i = 0; i < count; ++i) {
             hpadi_plan_s* P = B->plans[i];
             items.push_back({i, transform_row_args(P, round == 1 ? G[i] : P->R64, round == 1 ? ldg[i] : P->ldw)});
         }
         add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, 8, false);
+        seal();
         items.clear();
         for (int i = 0; i < count; ++i) items.push_back({i, transform_col_args(B->plans[i])});
         add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_TRANSFORM, 8, ts, true);
+        seal();
         for (int jj = 0; jj < jmax; ++jj) {
             std::vector<std::pair<int, hpadi::SweepArgs>> rows, cols, last;
             for (int i = 0; i < count; ++i) {
@@ -1443,12 +1473,15 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
                 (jj + 1 == F.J ? last : cols).push_back({i, adi_col_args(P, F, jj)});
             }
             add_sweeps(steps, table, B->plans, rows, hpadi::SWEEP_FULL, ts, ts, false);
+            seal();
             add_sweeps(steps, table, B->plans, cols, hpadi::SWEEP_FULL, ts, ts, true);
             add_sweeps(steps, table, B->plans, last, hpadi::SWEEP_SOLVE, ts, ts, true);
+            seal();
         }
         items.clear();
         for (int i = 0; i < count; ++i) items.push_back({i, final_args(B->plans[i], U[i], ldu[i], round > 1, true)});
         add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_FINAL, ts, 8, false);
+        seal();
     }
     if (!table.empty() &&
         (dmalloc(&B->table, table.size()) != hipSuccess ||
@@ -1458,34 +1491,59 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     }
     // capture the schedule on the origin stream (every plan works on that stream)
     for (hpadi_plan p : B->plans) p->stream = B->origin;
-    bool ok = hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed) == hipSuccess;
-    for (const BatchStep& st : steps) {
-        if (!ok) break;
+    // capture lanes: the origin stream plus kLanes - 1 side streams that join the capture
+    // through the fork event of each phase
+    bool ok = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k + 1 < hpadi_batch_s::kLanes && ok; ++k)
+        ok = hipStreamCreateWithFlags(&B->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&B->join[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        delete B;
+        return HPADI_EHIP;
+    }
+    auto lane = [&](int k) -> hipStream_t { return k == 0 ? B->origin : B->side[k - 1]; };
+    auto launch_step = [&](const BatchStep& st, hipStream_t q) -> bool {
         hpadi_plan_s* P = st.inst >= 0 ? B->plans[st.inst] : nullptr;
         switch (st.kind) {
             case 0: {
                 hpadi::GroupLaunch g = st.g;
                 g.tasks = B->table + st.task_off;
-                ok = hpadi::launch_sweep_uni_grouped(g, B->origin) == hipSuccess;
-                break;
+                return hpadi::launch_sweep_uni_grouped(g, q) == hipSuccess;
             }
             case 1:
-                ok = hpadi::launch_sweep(st.column ? P->dx.dev : P->dy.dev, st.a, st.mode, st.tin, st.tout, st.column,
-                                         B->origin) == hipSuccess;
-                break;
-            case 2:
-                ok = residual_into_r64(P, G[st.inst], ldg[st.inst], U[st.inst], ldu[st.inst]) == HPADI_OK;
-                break;
-            case 3:
-                ok = hpadi::launch_zero_f64(U[st.inst], ldu[st.inst], P->dx.op.N, P->dy.op.N, B->origin) == hipSuccess;
-                break;
+                return hpadi::launch_sweep(st.column ? P->dx.dev : P->dy.dev, st.a, st.mode, st.tin, st.tout,
+                                           st.column, q) == hipSuccess;
+            case 2: {
+                P->stream = q;
+                const bool r = residual_into_r64(P, G[st.inst], ldg[st.inst], U[st.inst], ldu[st.inst]) == HPADI_OK;
+                P->stream = B->origin;
+                return r;
+            }
             case 4:
-                ok = hpadi::launch_zero_f64(P->acc, 2, 1, 2, B->origin) == hipSuccess;
-                break;
+                return hpadi::launch_zero_accs(const_cast<double* const*>(B->acc_ptrs), count, q) == hipSuccess;
             default:
-                ok = false;
+                return false;
         }
-        ++B->nlaunch;
+    };
+    ok = hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed) == hipSuccess;
+    for (size_t a = 0; a < steps.size() && ok;) {
+        size_t b = a;
+        while (b < steps.size() && steps[b].phase == steps[a].phase) ++b;
+        const int nl = (int)std::min<size_t>(b - a, hpadi_batch_s::kLanes);
+        // fork: the side lanes of this phase wait for everything before it on the origin
+        if (nl > 1) {
+            ok = hipEventRecord(B->fork, B->origin) == hipSuccess;
+            for (int k = 1; k < nl && ok; ++k) ok = hipStreamWaitEvent(lane(k), B->fork, 0) == hipSuccess;
+        }
+        for (size_t t = a; t < b && ok; ++t) {
+            ok = launch_step(steps[t], lane((int)((t - a) % nl)));
+            ++B->nlaunch;
+        }
+        // join: the origin waits for every side lane before the next phase
+        for (int k = 1; k < nl && ok; ++k)
+            ok = hipEventRecord(B->join[k - 1], lane(k)) == hipSuccess &&
+                 hipStreamWaitEvent(B->origin, B->join[k - 1], 0) == hipSuccess;
+        a = b;
     }
     ok = ok && hpadi::launch_gather_acc(B->acc_ptrs, count, B->acc_all, B->origin) == hipSuccess;
     const bool ended = hipStreamEndCapture(B->origin, &B->graph) == hipSuccess;

@@ -86,6 +86,8 @@ struct hpadi_plan_s {
 namespace hpadi {
 // out[2 i + k] = accs[i][k], k = 0, 1 (gathers the plans' norm accumulators of a batch)
 hipError_t launch_gather_acc(const double* const* accs, int count, double* out, hipStream_t s);
+// accs[i][0] = accs[i][1] = 0 for i < count (the norm accumulators of a batch's plans)
+hipError_t launch_zero_accs(double* const* accs, int count, hipStream_t s);
 }  // namespace hpadi
 
 namespace hpadi_host {

@@ -135,7 +135,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 // Elementwise banded operators.
 // ---------------------------------------------------------------------------
 
-// K x and M x at position pos of a line x (stride sp), App. A entries.
+// K x and M x at position pos of a line x (stride sp), App. A entries (the 1/3, 1/6, 1/30
+// factors are multiplications by rounded reciprocals: a divide is a long FP64 sequence).
 __device__ __forceinline__ void gather_km(const DimDev& d, const double* x, long sp, int pos, double& Kx,
                                           double& Mx) {
     const int n = d.n, nh = d.nh, p = d.p;
@@ -148,27 +149,27 @@ __device__ __forceinline__ void gather_km(const DimDev& d, const double* x, long
             const int q = v - 1;
             const double dq = d.delta[q], idq = d.invdelta[q];
             Kx += idq * xh;
-            Mx += dq / 3.0 * xh;
+            Mx += dq * (1.0 / 3.0) * xh;
             if (vertex_is_hat(d.bc, n, v - 1)) {
                 const double xn = x[(long)(h - 1) * sp];
                 Kx -= idq * xn;
-                Mx += dq / 6.0 * xn;
+                Mx += dq * (1.0 / 6.0) * xn;
             }
-            if (p >= 2) Mx += dq / 6.0 * x[(long)(nh + q) * sp];
-            if (p >= 3) Mx += dq / 30.0 * x[(long)(nh + n + q) * sp];
+            if (p >= 2) Mx += dq * (1.0 / 6.0) * x[(long)(nh + q) * sp];
+            if (p >= 3) Mx += dq * (1.0 / 30.0) * x[(long)(nh + n + q) * sp];
         }
         if (v <= n - 1) {
             const int q = v;
             const double dq = d.delta[q], idq = d.invdelta[q];
             Kx += idq * xh;
-            Mx += dq / 3.0 * xh;
+            Mx += dq * (1.0 / 3.0) * xh;
             if (vertex_is_hat(d.bc, n, v + 1)) {
                 const double xn = x[(long)(h + 1) * sp];
                 Kx -= idq * xn;
-                Mx += dq / 6.0 * xn;
+                Mx += dq * (1.0 / 6.0) * xn;
             }
-            if (p >= 2) Mx += dq / 6.0 * x[(long)(nh + q) * sp];
-            if (p >= 3) Mx -= dq / 30.0 * x[(long)(nh + n + q) * sp];
+            if (p >= 2) Mx += dq * (1.0 / 6.0) * x[(long)(nh + q) * sp];
+            if (p >= 3) Mx -= dq * (1.0 / 30.0) * x[(long)(nh + n + q) * sp];
         }
     } else {
         const int b = pos - nh, m = b / n, e = b - m * n;
@@ -185,7 +186,7 @@ __device__ __forceinline__ void gather_km(const DimDev& d, const double* x, long
             double xl = 0.0, xr = 0.0;
             if (vertex_is_hat(d.bc, n, e)) xl = x[(long)hat_of_vertex(d.bc, e) * sp];
             if (vertex_is_hat(d.bc, n, e + 1)) xr = x[(long)hat_of_vertex(d.bc, e + 1) * sp];
-            Mx += (m == 0) ? de / 6.0 * (xl + xr) : de / 30.0 * (xr - xl);
+            Mx += (m == 0) ? de * (1.0 / 6.0) * (xl + xr) : de * (1.0 / 30.0) * (xr - xl);
         }
     }
 }
@@ -398,6 +399,21 @@ __global__ void gather_acc_kernel(const double* const* accs, int count, double* 
     out[2 * i + 1] = accs[i][1];
 }
 }  // namespace
+
+namespace {
+__global__ void zero_acc_kernel(double* const* accs, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    accs[i][0] = 0.0;
+    accs[i][1] = 0.0;
+}
+}  // namespace
+
+hipError_t launch_zero_accs(double* const* accs, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_acc_kernel, dim3((count + 255) / 256), dim3(256), 0, s, accs, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather_acc(const double* const* accs, int count, double* out, hipStream_t s) {
     hipLaunchKernelGGL(gather_acc_kernel, dim3((count + 255) / 256), dim3(256), 0, s, accs, count, out);

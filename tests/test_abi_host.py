@@ -94,3 +94,11 @@ def test_error_codes(hp):
         hp.hpadi_op1d_create(3, 4, 0.0, 1.0, breaks=[0.0, 0.5, 0.4, 1.0])
     assert ei.value.status == hp.HPADI_EINVAL
     assert "tolerance" in hp.hpadi_strerror(hp.HPADI_ENOCONV)
+
+
+def test_struct_layouts_match_the_header(hp):
+    """The ctypes mirrors of hpadi_options and hpadi_stats have the layout the library's
+    static_asserts fix (size and the offset of the last field added)."""
+    import ctypes
+    assert ctypes.sizeof(hp.hpadi_options) == 40 and hp.hpadi_options.refine_tol.offset == 32
+    assert ctypes.sizeof(hp.hpadi_stats) == 96 and hp.hpadi_stats.J_refine.offset == 68
