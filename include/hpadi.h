@@ -242,7 +242,7 @@ typedef struct {
  * convolutions with zero padding, tanh-form GELU after the hidden layers; BF16
  * activations and weights on the matrix cores with FP32 accumulation, FP32
  * master parameters.  Inside the Krylov loop the preconditioned residual z is
- * corrected by c = s_z NN([z/s_z, r/s_r, log a]) (s: root-mean-square values):
+ * corrected by c = s_z NN([z/s_z, (z/s_z)/a, log a]) (s_z: root-mean-square value of z):
  * z <- z + (beta/alpha) c with alpha z + beta c the energy-optimal combination
  * (it minimises ||v - e||_A over span{z, c} for the error e of the iterate, which
  * needs A z and A c: two extra operator applications per iteration); a
@@ -258,6 +258,11 @@ int hpadi_net_num_params(void);
 int hpadi_net_create(const float* params, unsigned long long seed, void* hip_stream, hpadi_net* out);
 int hpadi_net_get_params(hpadi_net net, float* params);
 int hpadi_net_set_params(hpadi_net net, const float* params);
+/* How the correction c enters the Krylov loop: omega = 0 (the default) combines z
+ * and c energy-optimally (two extra operator applications and two host round trips
+ * per iteration); omega > 0 uses z <- z + omega c, with the scale s_z kept on the
+ * device (no operator application, no host round trip).  EINVAL for omega < 0. */
+int hpadi_net_set_damping(hpadi_net net, double omega);
 /* out = NN(x): x FP32 device [B][H][W][3], out FP32 device [B][H][W]. */
 int hpadi_net_forward(hpadi_net net, const float* x_dev, int B, int H, int W, float* out_dev);
 /* Loss of a batch and its gradient with respect to the parameters (host copy),
@@ -274,7 +279,7 @@ int hpadi_net_train(hpadi_net net, const float* X_dev, const float* ZN_dev, cons
                     int npairs, int c, int batch, int steps, double lr, unsigned long long seed, float* loss_hist);
 /* Training pairs from the method: plain preconditioned CG (truncation 0) on
  * A_a x = b from x = 0; after the preconditioner of iteration k the images
- * [z/s_z, r/s_r, log a], zn = z/s_z, t = (xstar - x_k)/s_z and the slot weights
+ * [z/s_z, (z/s_z)/a, log a], zn = z/s_z, t = (xstar - x_k)/s_z and the slot weights
  * w = a (diag K_x diag M_y + diag M_x diag K_y), the diagonal of the energy form,
  * are formed and crops_per_iter
  * random c x c crops of them are appended to X (3 ch), ZN, T, Wt (FP32 device,

@@ -51,6 +51,7 @@ struct hpadi_net_s {
     int nd_cap = 0;
     int* idx = nullptr;
     int idx_cap = 0;
+    double damping = 0.0;         // > 0: z <- z + damping c; 0: energy-optimal combination
 
     void free_ws() {
         for (void* p : {(void*)x, (void*)zn, (void*)t, (void*)w, (void*)out, (void*)g, (void*)pre0, (void*)pre1,
@@ -229,6 +230,12 @@ int hpadi_net_set_params(hpadi_net N, const float* params) {
     return upload_params(N, params);
 }
 
+int hpadi_net_set_damping(hpadi_net N, double omega) {
+    if (!N || !(omega >= 0.0) || !std::isfinite(omega)) return HPADI_EINVAL;
+    N->damping = omega;
+    return HPADI_OK;
+}
+
 int hpadi_net_forward(hpadi_net N, const float* x, int B, int H, int W, float* out) {
     if (!N || !x || !out || B < 1 || H < 1 || W < 1) return HPADI_EINVAL;
     int rc = ensure_ws(N, (size_t)B * H * W, false);
@@ -317,22 +324,19 @@ int hpadi_net_pairs(hpadi_varcoef V, hpadi_plan precond, const double* b, int ld
     const size_t cc = (size_t)c * c;
     auto observe = [&](int k, const double* r, const double* z, const double* x) -> int {
         if (*count >= cap) return HPADI_OK;
-        double nz[1], nr[1];
+        double nz = 0.0;
         {
             hpadi::MultiB mb{};
             mb.nb = 1;
             mb.b[0] = z;
-            if (hpadi::launch_multidot(z, mb, n, V->part, V->dots, st) != hipSuccess) return HPADI_EHIP;
-            mb.b[0] = r;
-            if (hpadi::launch_multidot(r, mb, n, V->part, V->dots + 1, st) != hipSuccess) return HPADI_EHIP;
-            if (hipMemcpyAsync(V->dots_host, V->dots, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            if (hpadi::launch_multidot(z, mb, n, V->part, V->dots, st) != hipSuccess ||
+                hipMemcpyAsync(V->dots_host, V->dots, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 return HPADI_EHIP;
-            nz[0] = V->dots_host[0];
-            nr[0] = V->dots_host[1];
+            nz = V->dots_host[0];
         }
-        const double sz = std::sqrt(std::max(nz[0], 1e-300) / n), sr = std::sqrt(std::max(nr[0], 1e-300) / n);
-        if (hpadi::launch_pack_image(mp, z, r, V->Ny, 1.0 / sz, 1.0 / sr, V->img, st) != hipSuccess ||
+        const double sz = std::sqrt(std::max(nz, 1e-300) / n);
+        if (hpadi::launch_pack_image(mp, z, V->Ny, 1.0 / sz, V->img, st) != hipSuccess ||
             hpadi::launch_target_image(mp, xs, x, z, V->Ny, 1.0 / sz, V->wx, V->wy, V->img_zn, V->img_t, V->img_w,
                                        st) != hipSuccess)
             return HPADI_EHIP;
@@ -390,15 +394,26 @@ int net_correct(hpadi_net N, hpadi_varcoef_s* V, const double* r, double* z, boo
     mb.nb = 1;
     mb.b[0] = z;
     if (hpadi::launch_multidot(z, mb, n, V->part, V->dots, st) != hipSuccess) return HPADI_EHIP;
-    mb.b[0] = r;
-    if (hpadi::launch_multidot(r, mb, n, V->part, V->dots + 1, st) != hipSuccess) return HPADI_EHIP;
-    if ((rc = fetch(2)) != HPADI_OK) return rc;
-    const double zz = V->dots_host[0], rr = V->dots_host[1];
-    if (!(zz > 0.0) || !(rr > 0.0)) return HPADI_OK;
-    const double sz = std::sqrt(zz / n), sr = std::sqrt(rr / n);
     hpadi::SlotMap mp{V->H, V->W, V->sx, V->sy, V->loga};
+    if (N->damping > 0.0) {
+        // z <- z + damping c: the scale of z stays on the device, no host round trip
+        if (hpadi::launch_pack_image(mp, z, V->Ny, 0.0, V->img, st, V->dots, 1.0 / (double)n) != hipSuccess)
+            return HPADI_EHIP;
+        if (N->stream != st && hipStreamSynchronize(st) != hipSuccess) return HPADI_EHIP;
+        if ((rc = forward(N, V->img, ImgShape{1, V->H, V->W}, V->img_out, false)) != HPADI_OK) return rc;
+        if (N->stream != st && hipStreamSynchronize(N->stream) != hipSuccess) return HPADI_EHIP;
+        if (hpadi::launch_unpack_add(mp, V->img_out, N->damping, z, V->Ny, st, V->dots, 1.0 / (double)n) !=
+            hipSuccess)
+            return HPADI_EHIP;
+        *applied = true;
+        return HPADI_OK;
+    }
+    if ((rc = fetch(1)) != HPADI_OK) return rc;
+    const double zz = V->dots_host[0];
+    if (!(zz > 0.0)) return HPADI_OK;
+    const double sz = std::sqrt(zz / n);
     double* c = V->zs;
-    if (hpadi::launch_pack_image(mp, z, r, V->Ny, 1.0 / sz, 1.0 / sr, V->img, st) != hipSuccess) return HPADI_EHIP;
+    if (hpadi::launch_pack_image(mp, z, V->Ny, 1.0 / sz, V->img, st) != hipSuccess) return HPADI_EHIP;
     if (N->stream != st && hipStreamSynchronize(st) != hipSuccess) return HPADI_EHIP;
     if ((rc = forward(N, V->img, ImgShape{1, V->H, V->W}, V->img_out, false)) != HPADI_OK) return rc;
     if (N->stream != st && hipStreamSynchronize(N->stream) != hipSuccess) return HPADI_EHIP;

@@ -14,7 +14,7 @@
 namespace hpadi {
 
 constexpr int kNetC = 32;      // hidden channels
-constexpr int kNetCin = 3;     // input channels: z/s_z, r/s_r, log a
+constexpr int kNetCin = 3;     // input channels: z/s_z, (z/s_z)/a, log a
 // parameter vector (FP32): W0[3][3][3][32] b0[32] W1[3][3][32][32] b1[32] W2[...] b2[32] W3[3][3][32][1] b3[1]
 constexpr int kOffW0 = 0;
 constexpr int kOffB0 = kOffW0 + 9 * kNetCin * kNetC;
@@ -67,9 +67,14 @@ struct SlotMap {
     const int* sy;   // [W]
     const float* loga;  // [H W] log a at the slots
 };
-hipError_t launch_pack_image(const SlotMap& m, const double* z, const double* r, long ld, double inv_sz,
-                             double inv_sr, float* x, hipStream_t st);
-hipError_t launch_unpack_add(const SlotMap& m, const float* o, double sz, double* z, long ld, hipStream_t st);
+// x[p] = [z/s_z, (z/s_z) exp(-log a), log a] at every slot p, with 1/s_z = inv_sz, or, when zz
+// is given, 1/s_z = 1/sqrt(zz[0] inv_n) from the device sum of squares zz[0] of z (no host
+// round trip).
+hipError_t launch_pack_image(const SlotMap& m, const double* z, long ld, double inv_sz, float* x, hipStream_t st,
+                             const double* zz = nullptr, double inv_n = 0.0);
+// z[slot] += sz o[p]; when zz is given the factor is sz sqrt(zz[0] inv_n).
+hipError_t launch_unpack_add(const SlotMap& m, const float* o, double sz, double* z, long ld, hipStream_t st,
+                             const double* zz = nullptr, double inv_n = 0.0);
 // training pairs: crops (y0, x0) of size c from full images (H x W): inputs (3 ch), zn, t, w
 hipError_t launch_crop(const float* x, const float* zn, const float* t, const float* w, int H, int W, int c,
                        const int* pos /* [n][2] */, int n, float* cx, float* czn, float* ct, float* cw, hipStream_t st);

@@ -4,10 +4,12 @@
 // cores as implicit GEMMs: one wavefront computes 32 consecutive pixels of an
 // image row times the 32 output channels with v_mfma_f32_32x32x16_bf16, the
 // reduction running over 9 taps x 2 chunks of 16 input channels.  Operand
-// fragments are 16-byte loads straight from the NHWC BF16 activations (8
-// consecutive channels of one pixel per lane) and from the [tap][n][k] BF16
-// weights; accumulation is FP32.  The weight gradient of those layers is the
-// same contraction with the pixel index as the reduction, also on MFMA.  The
+// fragments are 16-byte LDS reads (8 consecutive channels of one pixel per lane)
+// of an input tile and of the [tap][n][k] BF16 weights, both staged per workgroup;
+// accumulation is FP32.  The weights are the A operand, so each lane ends
+// with runs of four consecutive output channels of one pixel, stored 8 bytes at a
+// time.  The weight gradient of those layers is the same contraction with the pixel
+// index as the reduction, also on MFMA.  The
 // 3 -> 32 input layer, the 32 -> 1 output layer and their gradients are small
 // and run on the vector ALUs in FP32.
 //
@@ -34,11 +36,13 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 constexpr float kGeluC = 0.7978845608028654f;  // sqrt(2/pi)
 constexpr float kGeluA = 0.044715f;
 
+// tanh(u) = 1 - 2 / (1 + e^(2u)) with the hardware exponential (saturates to +-1 for large |u|)
+__device__ inline float fast_tanh(float u) { return 1.0f - __fdividef(2.0f, 1.0f + __expf(2.0f * u)); }
 __device__ inline float gelu(float x) {
-    return 0.5f * x * (1.0f + tanhf(kGeluC * (x + kGeluA * x * x * x)));
+    return 0.5f * x * (1.0f + fast_tanh(kGeluC * (x + kGeluA * x * x * x)));
 }
 __device__ inline float gelu_grad(float x) {
-    const float t = tanhf(kGeluC * (x + kGeluA * x * x * x));
+    const float t = fast_tanh(kGeluC * (x + kGeluA * x * x * x));
     return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * kGeluC * (1.0f + 3.0f * kGeluA * x * x);
 }
 // round to nearest even (finite inputs)
@@ -82,59 +86,107 @@ __global__ void __launch_bounds__(256) conv_in_kernel(const float* __restrict__ 
             for (int c = 0; c < kNetC; ++c) acc[c] += v * wr[c];
         }
     }
+    // 16-byte stores: a pixel's 32 channels are 64 contiguous bytes of act (128 of pre)
+    if (pre) {
+        float4* pd = reinterpret_cast<float4*>(pre + p * kNetC);
 #pragma unroll
-    for (int c = 0; c < kNetC; ++c) {
-        if (pre) pre[p * kNetC + c] = acc[c];
-        act[p * kNetC + c] = f2bf(gelu(acc[c]));
+        for (int q = 0; q < kNetC / 4; ++q) pd[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+    }
+    u32x4* ad = reinterpret_cast<u32x4*>(act + p * kNetC);
+#pragma unroll
+    for (int q = 0; q < kNetC / 8; ++q) {
+        u32x4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            v[e] = (unsigned)f2bf(gelu(acc[8 * q + 2 * e])) | ((unsigned)f2bf(gelu(acc[8 * q + 2 * e + 1])) << 16);
+        ad[q] = v;
     }
 }
 
 // ---- hidden layers: 32 -> 32 on MFMA --------------------------------------
+// A workgroup of four wavefronts computes a tile of four image rows x 32 pixels: the
+// input rows of the tile plus a one-pixel halo (6 x 34 pixels) and the 9 x 32 x 32
+// weights are staged in LDS once, then each wavefront runs its row's 18 MFMAs from
+// LDS.  Staged pixels and weight rows are padded to 80 bytes, so the 16-byte LDS
+// reads of 16 consecutive lanes fall on distinct banks.
+constexpr int kConvRows = 4;                 // output rows per workgroup (one per wavefront)
+constexpr int kConvCols = 32;                // output pixels per row (the MFMA's 32)
+constexpr int kStage = 40;                   // BF16 per staged pixel or weight row (32 + 8 padding)
+constexpr int kTileW = kConvCols + 2, kTileH = kConvRows + 2;
+
 __global__ void __launch_bounds__(256) conv32_kernel(const bf16_t* __restrict__ in, ImgShape s,
                                                      const bf16_t* __restrict__ wt, const float* __restrict__ bias,
                                                      const float* __restrict__ pre_prev, float* __restrict__ pre,
                                                      bf16_t* __restrict__ act, int mode) {
-    const int lane = threadIdx.x & 63;
-    const long wave = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int nseg = (s.W + 31) / 32;
-    const long total = (long)s.B * s.H * nseg;
-    if (wave >= total) return;  // uniform per wavefront
-    const int seg = (int)(wave % nseg);
-    const long bh = wave / nseg;
-    const int h = (int)(bh % s.H), b = (int)(bh / s.H);
-    const int w0 = seg * 32;
+    __shared__ __attribute__((aligned(16))) bf16_t tile[kTileH * kTileW * kStage];
+    __shared__ __attribute__((aligned(16))) bf16_t wsh[9 * kNetC * kStage];
+    const int tiles_w = (s.W + kConvCols - 1) / kConvCols, tiles_h = (s.H + kConvRows - 1) / kConvRows;
+    long t = blockIdx.x;
+    const int tw = (int)(t % tiles_w);
+    t /= tiles_w;
+    const int th = (int)(t % tiles_h);
+    const int b = (int)(t / tiles_h);
+    const int h0 = th * kConvRows, w0 = tw * kConvCols;
+    // weights [tap][n][k]: 9 x 32 rows of 4 16-byte chunks
+    for (int i = threadIdx.x; i < 9 * kNetC * 4; i += blockDim.x) {
+        const int row = i >> 2, q = i & 3;
+        *reinterpret_cast<u32x4*>(wsh + row * kStage + 8 * q) =
+            *reinterpret_cast<const u32x4*>(wt + row * kNetC + 8 * q);
+    }
+    // input tile: rows h0-1 .. h0+4, pixels w0-1 .. w0+32, zero outside the image
+    for (int i = threadIdx.x; i < kTileH * kTileW * 4; i += blockDim.x) {
+        const int q = i & 3, px = (i >> 2) % kTileW, r = (i >> 2) / kTileW;
+        const int hh = h0 - 1 + r, ww = w0 - 1 + px;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (hh >= 0 && hh < s.H && ww >= 0 && ww < s.W)
+            v = *reinterpret_cast<const u32x4*>(in + (((long)b * s.H + hh) * s.W + ww) * kNetC + 8 * q);
+        *reinterpret_cast<u32x4*>(tile + (r * kTileW + px) * kStage + 8 * q) = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int h = h0 + wv;
+    if (h >= s.H) return;  // uniform per wavefront; no barrier follows
     const int m = lane & 31, kh = lane >> 5;
     f32x16 acc = {};
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-        const int hh = h + tap / 3 - 1, ww = w0 + m + tap % 3 - 1;
-        const bool ok = hh >= 0 && hh < s.H && ww >= 0 && ww < s.W;
-        const bf16_t* src = in + (((long)b * s.H + (ok ? hh : 0)) * s.W + (ok ? ww : 0)) * kNetC + 8 * kh;
-        const bf16_t* wsrc = wt + (tap * kNetC + m) * kNetC + 8 * kh;
+        const bf16_t* src = tile + ((wv + tap / 3) * kTileW + m + tap % 3) * kStage + 8 * kh;
+        const bf16_t* wsrc = wsh + (tap * kNetC + m) * kStage + 8 * kh;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            u32x4 av = {0u, 0u, 0u, 0u};
-            if (ok) av = *reinterpret_cast<const u32x4*>(src + 16 * c);
+            const u32x4 av = *reinterpret_cast<const u32x4*>(src + 16 * c);
             const u32x4 bv = *reinterpret_cast<const u32x4*>(wsrc + 16 * c);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                          __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+            // weights as A (rows: output channels), activations as B (columns: pixels)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, bv),
+                                                          __builtin_bit_cast(bf16x8, av), acc, 0, 0, 0);
         }
     }
-    const int n = lane & 31;
-    const float bn = (mode == 0 && bias) ? bias[n] : 0.0f;
+    // D[channel][pixel]: lane l holds pixel w0 + l % 32 and, in registers 4g..4g+3, the four
+    // consecutive channels 8 g + 4 (l / 32) + 0..3: 8-byte BF16 and 16-byte FP32 stores
+    const int w = w0 + m;
+    if (w >= s.W) return;
+    const long base = (((long)b * s.H + h) * s.W + w) * kNetC;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int mm = 8 * (i / 4) + 4 * kh + (i % 4);
-        const int w = w0 + mm;
-        if (w >= s.W) continue;
-        const long idx = (((long)b * s.H + h) * s.W + w) * kNetC + n;
+    for (int g = 0; g < 4; ++g) {
+        const int c0 = 8 * g + 4 * kh;
+        float v[4];
         if (mode == 0) {
-            const float v = acc[i] + bn;
-            if (pre) pre[idx] = v;
-            act[idx] = f2bf(gelu(v));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = acc[4 * g + e] + (bias ? bias[c0 + e] : 0.0f);
+            if (pre) *reinterpret_cast<float4*>(pre + base + c0) = make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = gelu(v[e]);
         } else {
-            act[idx] = f2bf(acc[i] * gelu_grad(pre_prev[idx]));
+            const float4 pp = *reinterpret_cast<const float4*>(pre_prev + base + c0);
+            v[0] = acc[4 * g + 0] * gelu_grad(pp.x);
+            v[1] = acc[4 * g + 1] * gelu_grad(pp.y);
+            v[2] = acc[4 * g + 2] * gelu_grad(pp.z);
+            v[3] = acc[4 * g + 3] * gelu_grad(pp.w);
         }
+        uint2 o;
+        o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+        o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+        *reinterpret_cast<uint2*>(act + base + c0) = o;
     }
 }
 
@@ -373,21 +425,33 @@ __global__ void zero_f32_kernel(float* p, size_t n) {
 }
 
 // ---- coefficient <-> image ----------------------------------------------------
-__global__ void pack_image_kernel(SlotMap mp, const double* z, const double* r, long ld, double isz, double isr,
+// The scale of z: isz, or (zz != NULL) 1 / sqrt(zz[0] inv_n) with zz[0] the device sum of
+// squares of z (0 for a zero z).
+__device__ inline double inv_rms(double isz, const double* zz, double inv_n) {
+    if (!zz) return isz;
+    const double ms = zz[0] * inv_n;
+    return ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+}
+
+__global__ void pack_image_kernel(SlotMap mp, const double* z, long ld, double isz_h, const double* zz, double inv_n,
                                   float* x) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
     if (j >= mp.W) return;
+    const double isz = inv_rms(isz_h, zz, inv_n);
     const int gi = mp.sx[i], gj = mp.sy[j];
     const bool ok = gi >= 0 && gj >= 0;
     const long p = (long)i * mp.W + j;
     x[3 * p + 0] = ok ? (float)(z[(long)gi * ld + gj] * isz) : 0.0f;
-    x[3 * p + 1] = ok ? (float)(r[(long)gi * ld + gj] * isr) : 0.0f;
+    x[3 * p + 1] = ok ? (float)(z[(long)gi * ld + gj] * isz * exp(-(double)mp.loga[p])) : 0.0f;
     x[3 * p + 2] = mp.loga[p];
 }
 
-__global__ void unpack_add_kernel(SlotMap mp, const float* o, double sz, double* z, long ld) {
+__global__ void unpack_add_kernel(SlotMap mp, const float* o, double sz_h, const double* zz, double inv_n, double* z,
+                                  long ld) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
     if (j >= mp.W) return;
+    // scale sz_h, or (zz != NULL) sz_h times the root-mean-square value of z
+    const double sz = zz ? sz_h * sqrt(fmax(zz[0] * inv_n, 0.0)) : sz_h;
     const int gi = mp.sx[i], gj = mp.sy[j];
     if (gi < 0 || gj < 0) return;
     z[(long)gi * ld + gj] += sz * (double)o[(long)i * mp.W + j];
@@ -445,9 +509,9 @@ hipError_t launch_conv_in(const float* x, ImgShape s, const float* params, float
 
 hipError_t launch_conv32(const bf16_t* in, ImgShape s, const bf16_t* wt, const float* bias, const float* pre_prev,
                          float* pre, bf16_t* act, int mode, hipStream_t st) {
-    const long waves = (long)s.B * s.H * ((s.W + 31) / 32);
-    hipLaunchKernelGGL(conv32_kernel, dim3(blocks_for(waves, 4)), dim3(256), 0, st, in, s, wt, bias, pre_prev, pre,
-                       act, mode);
+    const long tiles = (long)s.B * ((s.H + kConvRows - 1) / kConvRows) * ((s.W + kConvCols - 1) / kConvCols);
+    hipLaunchKernelGGL(conv32_kernel, dim3((unsigned)tiles), dim3(256), 0, st, in, s, wt, bias, pre_prev, pre, act,
+                       mode);
     return hipGetLastError();
 }
 
@@ -523,15 +587,17 @@ hipError_t launch_zero_f32(float* p, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_pack_image(const SlotMap& m, const double* z, const double* r, long ld, double inv_sz,
-                             double inv_sr, float* x, hipStream_t st) {
-    hipLaunchKernelGGL(pack_image_kernel, dim3(blocks_for(m.W, 256), m.H), dim3(256), 0, st, m, z, r, ld, inv_sz,
-                       inv_sr, x);
+hipError_t launch_pack_image(const SlotMap& m, const double* z, long ld, double inv_sz, float* x, hipStream_t st,
+                             const double* zz, double inv_n) {
+    hipLaunchKernelGGL(pack_image_kernel, dim3(blocks_for(m.W, 256), m.H), dim3(256), 0, st, m, z, ld, inv_sz, zz,
+                       inv_n, x);
     return hipGetLastError();
 }
 
-hipError_t launch_unpack_add(const SlotMap& m, const float* o, double sz, double* z, long ld, hipStream_t st) {
-    hipLaunchKernelGGL(unpack_add_kernel, dim3(blocks_for(m.W, 256), m.H), dim3(256), 0, st, m, o, sz, z, ld);
+hipError_t launch_unpack_add(const SlotMap& m, const float* o, double sz, double* z, long ld, hipStream_t st,
+                             const double* zz, double inv_n) {
+    hipLaunchKernelGGL(unpack_add_kernel, dim3(blocks_for(m.W, 256), m.H), dim3(256), 0, st, m, o, sz, zz, inv_n, z,
+                       ld);
     return hipGetLastError();
 }
 

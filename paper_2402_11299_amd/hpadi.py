@@ -85,6 +85,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "hpadi_net_get_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
     "hpadi_net_set_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
+    "hpadi_net_set_damping": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "hpadi_net_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p]),
     "hpadi_net_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -492,6 +493,10 @@ class Net:
         import numpy as np
         arr = np.ascontiguousarray(params, dtype=np.float32)
         check(lib().hpadi_net_set_params(self.handle, arr.ctypes.data_as(_c_float_p)), "hpadi_net_set_params")
+
+    def set_damping(self, omega):
+        """0: energy-optimal combination of z and the correction; omega > 0: z + omega c."""
+        check(lib().hpadi_net_set_damping(self.handle, float(omega)), "hpadi_net_set_damping")
 
     def forward(self, x):
         import torch

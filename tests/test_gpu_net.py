@@ -169,6 +169,14 @@ def test_learned_fcg_small(hp):
     # the correction is combined energy-optimally with the plain preconditioned residual:
     # it may fail to help, but it must not cost more than a few iterations
     assert st.iters <= stp.iters + 3
+    # damped addition z + c/2 (scale kept on the device): still reaches the tolerance
+    net.set_damping(0.5)
+    xd, std, _ = vc.solve(b, pre, tol=1e-10, maxit=300, truncation=1, net=net)
+    trd = np.linalg.norm(bh - op.apply(xd.cpu().numpy())) / np.linalg.norm(bh)
+    print(f"  damped: {std.iters} it ({std.corrections} corrections); true res {trd:.2e}", flush=True)
+    assert std.status == hp.HPADI_OK and trd <= 1e-10 * (1 + 1e-3) and std.corrections == std.iters
+    with pytest.raises(hp.HpadiError):
+        net.set_damping(-1.0)
     net.close()
     pre.close()
     vc.close()
