@@ -171,20 +171,24 @@ def varcoef_fcg(hp, torch, steps=3):
     vc = hp.VarCoef(x, y, a)
     pre = hp.Plan(x, y, 0.0, 1e-4, "fp64")
     b = pre.load(torch.from_numpy(workloads.legendre_rhs(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.seed)).cuda())
+    # the same loop with a cheaper preconditioner (ADI at tol 1e-2): the iteration count is set by
+    # the coefficient's contrast, not by the accuracy of the constant-coefficient solve
+    pre2 = hp.Plan(x, y, 0.0, 1e-2, "fp64")
     res = {}
-    for name, m in (("pcg", 0), ("fcg1", 1)):
-        vc.solve(b, pre, tol=cfg.tol, maxit=300, truncation=m)
+    for name, m, pc in (("pcg", 0, pre), ("fcg1", 1, pre), ("pcg_adi_tol1e-2", 0, pre2)):
+        vc.solve(b, pc, tol=cfg.tol, maxit=300, truncation=m)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            _, st, _ = vc.solve(b, pre, tol=cfg.tol, maxit=300, truncation=m)
+            _, st, _ = vc.solve(b, pc, tol=cfg.tol, maxit=300, truncation=m)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / steps
         res[name] = {"iters": st.iters, "ms": t * 1e3, "true_rel_res": st.true_rel_res,
-                     "dof_per_s": x.N * y.N / t}
-    log(f"varcoef n=p=32: pcg {res['pcg']['iters']} it {res['pcg']['ms']:.1f} ms; "
-        f"fcg1 {res['fcg1']['iters']} it {res['fcg1']['ms']:.1f} ms")
+                     "dof_per_s": x.N * y.N / t, "adi_J": pc.J}
+    log("varcoef n=p=32: " + "; ".join(f"{k} {v['iters']} it {v['ms']:.1f} ms (ADI J={v['adi_J']})"
+                                       for k, v in res.items()))
     pre.close()
+    pre2.close()
     vc.close()
     return {"workload": "varcoef_n32_p32_grf: -div(a grad u) = f, a = 1 + exp(g)/2, N = 1023, tol 1e-10",
             **res}
