@@ -444,7 +444,8 @@ def main():
                    "N": x.N, "n": cfgD.nx, "p": cfgD.px, "tol": cfgD.tol, "J_inner": pm.J,
                    "J_refine": st_mixed.J_refine, "rounds": st_mixed.rounds, "fp32_rounds": st_mixed.fp32_rounds,
                    "est_rel_err": st_mixed.est_rel_err,
-                   "rel_err_vs_oracle_roundtrip": err_rt, "plan_ms": t_plan_mixed * 1e3},
+                   "rel_err_vs_oracle_roundtrip": err_rt, "plan_ms": t_plan_mixed * 1e3,
+                   "end_to_end_dof_per_s": N2 / (t_plan_mixed + t_mixed)},
         "roofline": roof,
         "kernels": per_kernel,
         "cpu_baseline": cpu,
