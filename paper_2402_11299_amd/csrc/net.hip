@@ -60,27 +60,48 @@ __device__ inline void pix_of(long p, const ImgShape& s, int& b, int& h, int& w)
 }
 
 // ---- first layer: 3 -> 32 -------------------------------------------------
+// A workgroup computes 4 rows x 64 pixels; the 3-channel input of the tile plus a
+// one-pixel halo (6 x 66 pixels, zero outside the image) is staged in LDS as float4.
+constexpr int kInRows = 4, kInCols = 64;
+constexpr int kInTileW = kInCols + 2, kInTileH = kInRows + 2;
+
 __global__ void __launch_bounds__(256) conv_in_kernel(const float* __restrict__ x, ImgShape s,
                                                       const float* __restrict__ P, float* __restrict__ pre,
                                                       bf16_t* __restrict__ act) {
     __shared__ float wsh[9 * kNetCin * kNetC + kNetC];
+    __shared__ float4 tin[kInTileH * kInTileW];
     for (int i = threadIdx.x; i < 9 * kNetCin * kNetC + kNetC; i += blockDim.x) wsh[i] = P[kOffW0 + i];
+    const int tiles_w = (s.W + kInCols - 1) / kInCols, tiles_h = (s.H + kInRows - 1) / kInRows;
+    long t = blockIdx.x;
+    const int tw = (int)(t % tiles_w);
+    t /= tiles_w;
+    const int th = (int)(t % tiles_h);
+    const int b = (int)(t / tiles_h);
+    const int h0 = th * kInRows, w0 = tw * kInCols;
+    for (int i = threadIdx.x; i < kInTileH * kInTileW; i += blockDim.x) {
+        const int r = i / kInTileW, px = i % kInTileW;
+        const int hh = h0 - 1 + r, ww = w0 - 1 + px;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (hh >= 0 && hh < s.H && ww >= 0 && ww < s.W) {
+            const float* src = x + (((long)b * s.H + hh) * s.W + ww) * kNetCin;
+            v = make_float4(src[0], src[1], src[2], 0.0f);
+        }
+        tin[i] = v;
+    }
     __syncthreads();
-    const long np = (long)s.B * s.H * s.W;
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    int b, h, w;
-    pix_of(p, s, b, h, w);
+    const int r = threadIdx.x / kInCols, cc = threadIdx.x % kInCols;
+    const int h = h0 + r, w = w0 + cc;
+    if (h >= s.H || w >= s.W) return;
+    const long p = ((long)b * s.H + h) * s.W + w;
     float acc[kNetC];
 #pragma unroll
     for (int c = 0; c < kNetC; ++c) acc[c] = wsh[9 * kNetCin * kNetC + c];
     for (int tap = 0; tap < 9; ++tap) {
-        const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
-        if (hh < 0 || hh >= s.H || ww < 0 || ww >= s.W) continue;
-        const float* src = x + (((long)b * s.H + hh) * s.W + ww) * kNetCin;
+        const float4 v4 = tin[(r + tap / 3) * kInTileW + cc + tap % 3];
+        const float vin[kNetCin] = {v4.x, v4.y, v4.z};
 #pragma unroll
         for (int ci = 0; ci < kNetCin; ++ci) {
-            const float v = src[ci];
+            const float v = vin[ci];
             const float* wr = wsh + (tap * kNetCin + ci) * kNetC;
 #pragma unroll
             for (int c = 0; c < kNetC; ++c) acc[c] += v * wr[c];
@@ -104,17 +125,17 @@ __global__ void __launch_bounds__(256) conv_in_kernel(const float* __restrict__ 
 }
 
 // ---- hidden layers: 32 -> 32 on MFMA --------------------------------------
-// A workgroup of four wavefronts computes a tile of four image rows x 32 pixels: the
-// input rows of the tile plus a one-pixel halo (6 x 34 pixels) and the 9 x 32 x 32
+// A workgroup of eight wavefronts computes a tile of eight image rows x 32 pixels: the
+// input rows of the tile plus a one-pixel halo (10 x 34 pixels) and the 9 x 32 x 32
 // weights are staged in LDS once, then each wavefront runs its row's 18 MFMAs from
 // LDS.  Staged pixels and weight rows are padded to 80 bytes, so the 16-byte LDS
 // reads of 16 consecutive lanes fall on distinct banks.
-constexpr int kConvRows = 4;                 // output rows per workgroup (one per wavefront)
+constexpr int kConvRows = 8;                 // output rows per workgroup (one per wavefront)
 constexpr int kConvCols = 32;                // output pixels per row (the MFMA's 32)
 constexpr int kStage = 40;                   // BF16 per staged pixel or weight row (32 + 8 padding)
 constexpr int kTileW = kConvCols + 2, kTileH = kConvRows + 2;
 
-__global__ void __launch_bounds__(256) conv32_kernel(const bf16_t* __restrict__ in, ImgShape s,
+__global__ void __launch_bounds__(64 * kConvRows) conv32_kernel(const bf16_t* __restrict__ in, ImgShape s,
                                                      const bf16_t* __restrict__ wt, const float* __restrict__ bias,
                                                      const float* __restrict__ pre_prev, float* __restrict__ pre,
                                                      bf16_t* __restrict__ act, int mode) {
@@ -191,25 +212,43 @@ __global__ void __launch_bounds__(256) conv32_kernel(const bf16_t* __restrict__ 
 }
 
 // ---- last layer: 32 -> 1 --------------------------------------------------
+// A workgroup computes 4 rows x 64 pixels from an LDS tile of the input (6 x 66 pixels,
+// zero outside the image, pixels padded to 80 bytes); each thread sums its pixel's
+// 9 taps x 32 channels in FP32, in the same order as a direct loop.
+constexpr int kOutRows = 4, kOutCols = 64;
+constexpr int kOutTileW = kOutCols + 2, kOutTileH = kOutRows + 2;
+
 __global__ void __launch_bounds__(256) conv_out_kernel(const bf16_t* __restrict__ a, ImgShape s,
                                                        const float* __restrict__ P, float* __restrict__ out) {
     __shared__ float wsh[9 * kNetC + 1];
+    __shared__ __attribute__((aligned(16))) bf16_t tile[kOutTileH * kOutTileW * kStage];
     for (int i = threadIdx.x; i < 9 * kNetC + 1; i += blockDim.x) wsh[i] = P[kOffW3 + i];
+    const int tiles_w = (s.W + kOutCols - 1) / kOutCols, tiles_h = (s.H + kOutRows - 1) / kOutRows;
+    long t = blockIdx.x;
+    const int tw = (int)(t % tiles_w);
+    t /= tiles_w;
+    const int th = (int)(t % tiles_h);
+    const int b = (int)(t / tiles_h);
+    const int h0 = th * kOutRows, w0 = tw * kOutCols;
+    for (int i = threadIdx.x; i < kOutTileH * kOutTileW * 4; i += blockDim.x) {
+        const int q = i & 3, px = (i >> 2) % kOutTileW, r = (i >> 2) / kOutTileW;
+        const int hh = h0 - 1 + r, ww = w0 - 1 + px;
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (hh >= 0 && hh < s.H && ww >= 0 && ww < s.W)
+            v = *reinterpret_cast<const u32x4*>(a + (((long)b * s.H + hh) * s.W + ww) * kNetC + 8 * q);
+        *reinterpret_cast<u32x4*>(tile + (r * kOutTileW + px) * kStage + 8 * q) = v;
+    }
     __syncthreads();
-    const long np = (long)s.B * s.H * s.W;
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    int b, h, w;
-    pix_of(p, s, b, h, w);
+    const int r = threadIdx.x / kOutCols, c = threadIdx.x % kOutCols;
+    const int h = h0 + r, w = w0 + c;
+    if (h >= s.H || w >= s.W) return;
     float acc = wsh[9 * kNetC];
     for (int tap = 0; tap < 9; ++tap) {
-        const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
-        if (hh < 0 || hh >= s.H || ww < 0 || ww >= s.W) continue;
-        const u32x4* src = reinterpret_cast<const u32x4*>(a + (((long)b * s.H + hh) * s.W + ww) * kNetC);
+        const bf16_t* src = tile + ((r + tap / 3) * kOutTileW + c + tap % 3) * kStage;
         const float* wr = wsh + tap * kNetC;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const u32x4 v = src[q];
+            const u32x4 v = *reinterpret_cast<const u32x4*>(src + 8 * q);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 acc += __uint_as_float(v[e] << 16) * wr[8 * q + 2 * e];
@@ -217,7 +256,7 @@ __global__ void __launch_bounds__(256) conv_out_kernel(const bf16_t* __restrict_
             }
         }
     }
-    out[p] = acc;
+    out[((long)b * s.H + h) * s.W + w] = acc;
 }
 
 // ---- loss -----------------------------------------------------------------
@@ -502,22 +541,22 @@ inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs
 }  // namespace
 
 hipError_t launch_conv_in(const float* x, ImgShape s, const float* params, float* pre, bf16_t* act, hipStream_t st) {
-    const long np = (long)s.B * s.H * s.W;
-    hipLaunchKernelGGL(conv_in_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, x, s, params, pre, act);
+    const long tiles = (long)s.B * ((s.H + kInRows - 1) / kInRows) * ((s.W + kInCols - 1) / kInCols);
+    hipLaunchKernelGGL(conv_in_kernel, dim3((unsigned)tiles), dim3(256), 0, st, x, s, params, pre, act);
     return hipGetLastError();
 }
 
 hipError_t launch_conv32(const bf16_t* in, ImgShape s, const bf16_t* wt, const float* bias, const float* pre_prev,
                          float* pre, bf16_t* act, int mode, hipStream_t st) {
     const long tiles = (long)s.B * ((s.H + kConvRows - 1) / kConvRows) * ((s.W + kConvCols - 1) / kConvCols);
-    hipLaunchKernelGGL(conv32_kernel, dim3((unsigned)tiles), dim3(256), 0, st, in, s, wt, bias, pre_prev, pre, act,
-                       mode);
+    hipLaunchKernelGGL(conv32_kernel, dim3((unsigned)tiles), dim3(64 * kConvRows), 0, st, in, s, wt, bias, pre_prev,
+                       pre, act, mode);
     return hipGetLastError();
 }
 
 hipError_t launch_conv_out(const bf16_t* a, ImgShape s, const float* params, float* out, hipStream_t st) {
-    const long np = (long)s.B * s.H * s.W;
-    hipLaunchKernelGGL(conv_out_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, st, a, s, params, out);
+    const long tiles = (long)s.B * ((s.H + kOutRows - 1) / kOutRows) * ((s.W + kOutCols - 1) / kOutCols);
+    hipLaunchKernelGGL(conv_out_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a, s, params, out);
     return hipGetLastError();
 }
 
