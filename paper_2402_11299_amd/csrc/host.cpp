@@ -294,13 +294,18 @@ bool lanczos_lmax(const hpadi_op1d_s& o, const SparseOp& A, const SparseOp& M, c
         double b2 = 0.0;
         for (int i = 0; i < N; ++i) b2 += w[i] * Mq[i];
         al.push_back(alpha);
-        const double th = tridiag_max_eig(al, be);
-        if (k > 0 && std::fabs(th - last) <= 1e-11 * std::fabs(th)) {
-            if (++stable >= 4) { last = th; break; }
-        } else {
-            stable = 0;
+        // the Ritz value is checked every 4th step (each check is a bisection over the
+        // tridiagonal matrix built so far); converged after 3 checks in a row move it by at
+        // most 1e-11 relative
+        if (k % 4 == 3 || !(b2 > 0.0) || k + 1 == kmax) {
+            const double th = tridiag_max_eig(al, be);
+            if (k > 3 && std::fabs(th - last) <= 1e-11 * std::fabs(th)) {
+                if (++stable >= 3) { last = th; break; }
+            } else {
+                stable = 0;
+            }
+            last = th;
         }
-        last = th;
         if (!(b2 > 0.0)) break;
         beta = std::sqrt(b2);
         be.push_back(beta);
@@ -405,6 +410,35 @@ int interval_of(const hpadi_op1d_s& o, double omega2, double out[2]) {
     const double ell = o.x[o.n] - o.x[0];
     const double lo = (o.bc == HPADI_DIRICHLET) ? kPi * kPi / (ell * ell) + omega2 / 2.0 : omega2 / 2.0;
     if (o.N == 0) return HPADI_EINVAL;
+    const double dmin = *std::min_element(o.delta.begin(), o.delta.end());
+    const double dmax = *std::max_element(o.delta.begin(), o.delta.end());
+    if (o.n >= 16 && dmax - dmin <= 1e-12 * dmax) {
+        // Upper end from the elements: x^T K x = sum_e x_e^T K_e x_e and likewise for M, so the
+        // largest eigenvalue of (K, M) is at most the largest element-level one (a Dirichlet
+        // constraint only lowers it).  An element of width delta has the pair (K_1/delta,
+        // delta M_1) of the unit element, eigenvalues lambda(K_1, M_1)/delta^2: one Lanczos run
+        // of size p + 1.  On uniform meshes of 16 or more elements it is within 0.7% of the
+        // assembled eigenvalue (0.004% at n = p = 64); coarser or graded meshes, where the
+        // boundary elements make it looser (up to 30% measured), take the assembled Lanczos.
+        hpadi_op1d_s u;
+        u.n = 1;
+        u.p = o.p;
+        u.bc = HPADI_NEUMANN;
+        u.x = {0.0, 1.0};
+        u.delta = {1.0};
+        u.nh = 2;
+        u.N = u.nh + (o.p - 1);
+        u.Nleg = o.p + 1;
+        SparseOp K1 = build_op(u, 1.0, 0.0);
+        SparseOp M1 = build_op(u, 0.0, 1.0);
+        HostFactor M1f;
+        if (!host_factor(u, M1, M1f)) return HPADI_ENOTSPD;
+        double lk = 0.0;
+        if (!lanczos_lmax(u, K1, M1, M1f, &lk)) return HPADI_EINVAL;
+        out[0] = lo;
+        out[1] = std::max((lk / (dmin * dmin) + omega2 / 2.0) * (1.0 + 1e-6), lo * 1.0000001);
+        return HPADI_OK;
+    }
     SparseOp A = build_op(o, 1.0, omega2 / 2.0);
     SparseOp M = build_op(o, 0.0, 1.0);
     HostFactor Mf;

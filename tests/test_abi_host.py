@@ -76,6 +76,22 @@ def test_host_interval_contains_spectrum(hp, bc, w2, n, p):
     assert lmax <= hi <= 1.02 * lmax
 
 
+@pytest.mark.parametrize("bc,w2", [("dirichlet", 0.0), ("neumann", 1.0), ("dirichlet", 10.0)])
+@pytest.mark.parametrize("n,p", [(16, 8), (32, 4), (20, 12)])
+def test_host_interval_element_bound(hp, bc, w2, n, p):
+    """Uniform meshes of 16 or more elements take the upper end from the element-level
+    eigenvalue: it must contain the dense spectrum and stay within 1% of its top; a graded
+    mesh of the same size takes the assembled Lanczos (within 2%)."""
+    for breaks, slack in ((None, 1.01), (np.concatenate([[0.0], np.cumsum(np.linspace(1.0, 2.0, n))]) /
+                                         np.sum(np.linspace(1.0, 2.0, n)), 1.02)):
+        op = hp.Op1D(n, p, 0.0, 1.0, bc, breaks=None if breaks is None else list(breaks))
+        lo, hi = hp.hpadi_interval(op.handle, w2)
+        ops = obasis.assemble(obasis.make_basis(n, p, 0.0, 1.0, bc, breaks=breaks))
+        lmin, lmax = ospectrum.extreme_eigenvalues(ops, w2)
+        assert lo <= lmin * (1 + 1e-9)
+        assert lmax <= hi <= slack * lmax
+
+
 def test_error_codes(hp):
     with pytest.raises(hp.HpadiError) as ei:
         hp.hpadi_op1d_create(0, 4)
