@@ -178,7 +178,10 @@ void hpadi_plan_destroy(hpadi_plan plan);
  * instances advance in lock step: every ADI iteration is a few grouped launches,
  * one per (direction, chain length p/2, lines per workgroup) present, each running
  * that half-sweep for all instances in it (a device task table maps workgroups to
- * instances); transforms and final solves likewise; residuals per instance.
+ * instances); transforms and final solves likewise; residuals per instance.  The
+ * launches of one step touch disjoint instances and are captured as parallel
+ * branches over four streams (the origin and three of the batch's own, default
+ * priority), joined before the next step.  Both rounds use one shift family (3e-6).
  * autotune != 0: for every distinct (n_x, p_x, n_y, p_y, bc) the lines per
  * workgroup (4 or 8) is chosen by timing both on the instance (this runs solves
  * and overwrites U[i]).  G[i], U[i]: FP64 device arrays N_x x N_y (ld ldg[i],

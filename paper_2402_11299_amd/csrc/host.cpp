@@ -900,7 +900,7 @@ struct hpadi_batch_s {
     hpadi::GroupTask* table = nullptr;   // device task tables of the grouped launches
     int nlaunch = 0;                     // launches in the graph
     double tol = 0.0;
-    const double** acc_ptrs = nullptr;   // device array of the plans' accumulators
+    double** acc_ptrs = nullptr;         // device array of the plans' accumulators
     double* acc_all = nullptr;           // device [count][2]
     double* acc_host = nullptr;          // pinned copy
     ~hpadi_batch_s() {
@@ -1443,7 +1443,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         }
     }
     // device table of accumulator pointers and their gathered copy
-    std::vector<const double*> accs(count);
+    std::vector<double*> accs(count);
     for (int i = 0; i < count; ++i) accs[i] = B->plans[i]->acc;
     if (dmalloc(&B->acc_ptrs, (size_t)count) != hipSuccess || dmalloc(&B->acc_all, 2 * (size_t)count) != hipSuccess ||
         hipHostMalloc((void**)&B->acc_host, 2 * (size_t)count * sizeof(double)) != hipSuccess ||
@@ -1554,7 +1554,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
                 return r;
             }
             case 4:
-                return hpadi::launch_zero_accs(const_cast<double* const*>(B->acc_ptrs), count, q) == hipSuccess;
+                return hpadi::launch_zero_accs(B->acc_ptrs, count, q) == hipSuccess;
             default:
                 return false;
         }
