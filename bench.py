@@ -314,9 +314,9 @@ def main():
                     help="run only a 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the solver runs on a single MI355X; "
-              "a multi-GPU run is not part of this build (see DESIGN.md for how it would shard).",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single MI355X. Several GPUs would take "
+              "independent solves by instance, and one large solve by contiguous element ranges per axis "
+              "(only the hat chain crossing GPUs); that is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
