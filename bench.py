@@ -239,10 +239,12 @@ def learned_fcg(hp, torch, nfield=9, steps=2000, crop=128):
     for kind, seed in (("grf", 300), ("singular", 302)):
         vc = field(kind, seed)
         out = {}
-        for name, m, nn, om in (("plain_pcg", 0, None, 0.0), ("learned_fcg1", 1, net, 0.0),
-                                ("learned_fcg1_damped", 1, net, 0.5)):
+        for name, m, nn, om, per in (("plain_pcg", 0, None, 0.0, 1), ("learned_fcg1", 1, net, 0.0, 1),
+                                     ("learned_fcg1_damped", 1, net, 0.5, 1),
+                                     ("learned_fcg1_damped_every2", 1, net, 0.5, 2)):
             if nn is not None:
                 nn.set_damping(om)
+                nn.set_period(per)
             vc.solve(b, pre, tol=1e-10, maxit=400, truncation=m, net=nn)
             torch.cuda.synchronize()
             t1 = time.perf_counter()

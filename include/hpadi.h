@@ -266,6 +266,10 @@ int hpadi_net_set_params(hpadi_net net, const float* params);
  * per iteration); omega > 0 uses z <- z + omega c, with the scale s_z kept on the
  * device (no operator application, no host round trip).  EINVAL for omega < 0. */
 int hpadi_net_set_damping(hpadi_net net, double omega);
+/* Apply the correction at Krylov iterations 0, period, 2 period, ... only (period >= 1,
+ * default 1); the other iterations use the plain preconditioned residual.  EINVAL for
+ * period < 1. */
+int hpadi_net_set_period(hpadi_net net, int period);
 /* out = NN(x): x FP32 device [B][H][W][3], out FP32 device [B][H][W]. */
 int hpadi_net_forward(hpadi_net net, const float* x_dev, int B, int H, int W, float* out_dev);
 /* Loss of a batch and its gradient with respect to the parameters (host copy),

@@ -323,7 +323,7 @@ int fcg_core(hpadi_varcoef_s* V, hpadi_plan precond, hpadi_net net, const double
         if ((rc = precondition()) != HPADI_OK) return rc;
         if (net) {
             bool applied = false;
-            if ((rc = net_correct(net, V, V->r, V->z, &applied)) != HPADI_OK) return rc;
+            if ((rc = net_correct(net, V, V->r, V->z, k, &applied)) != HPADI_OK) return rc;
             if (applied) st.corrections++;
         }
         if (observe && (rc = observe(k, V->r, V->z, xc)) != HPADI_OK) return rc;

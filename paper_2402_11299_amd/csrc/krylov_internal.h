@@ -76,11 +76,12 @@ int fcg_core(hpadi_varcoef_s* V, hpadi_plan precond, hpadi_net net, const double
              double tol, int maxit, int truncation, double* res_hist, int hist_len, hpadi_krylov_stats* stats,
              const KrylovObserver& observe);
 
-// Learned correction of the preconditioned residual: c = s_z NN([z/s_z, r/s_r, log a])
-// on the slot image (s = root-mean-square values), combined as z <- z + (beta/alpha) c
-// with (alpha, beta) minimising the energy error f(v) = v.Av - 2 v.r of alpha z + beta c
-// (the error equation is A e = r, and f(v) = ||v - e||_A^2 - e.r).  *applied = false
-// when the combination is degenerate or not finite; z is then left as it was.
-int net_correct(hpadi_net net, hpadi_varcoef_s* V, const double* r, double* z, bool* applied);
+// Learned correction of the preconditioned residual at Krylov iteration iter (only at
+// multiples of the net's period): c = s_z NN([z/s_z, (z/s_z)/a, log a]) on the slot image
+// (s_z = root-mean-square value of z).  Damping 0: z <- z + (beta/alpha) c with (alpha, beta)
+// minimising the energy error f(v) = v.Av - 2 v.r of alpha z + beta c (the error equation is
+// A e = r, and f(v) = ||v - e||_A^2 - e.r); *applied = false when the combination is
+// degenerate or not finite, z is then left as it was.  Damping omega > 0: z <- z + omega c.
+int net_correct(hpadi_net net, hpadi_varcoef_s* V, const double* r, double* z, int iter, bool* applied);
 
 }  // namespace hpadi_host

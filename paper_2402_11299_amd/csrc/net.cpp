@@ -52,6 +52,7 @@ struct hpadi_net_s {
     int* idx = nullptr;
     int idx_cap = 0;
     double damping = 0.0;         // > 0: z <- z + damping c; 0: energy-optimal combination
+    int period = 1;               // correct the preconditioned residual at every period-th iteration
 
     void free_ws() {
         for (void* p : {(void*)x, (void*)zn, (void*)t, (void*)w, (void*)out, (void*)g, (void*)pre0, (void*)pre1,
@@ -230,6 +231,12 @@ int hpadi_net_set_params(hpadi_net N, const float* params) {
     return upload_params(N, params);
 }
 
+int hpadi_net_set_period(hpadi_net N, int period) {
+    if (!N || period < 1) return HPADI_EINVAL;
+    N->period = period;
+    return HPADI_OK;
+}
+
 int hpadi_net_set_damping(hpadi_net N, double omega) {
     if (!N || !(omega >= 0.0) || !std::isfinite(omega)) return HPADI_EINVAL;
     N->damping = omega;
@@ -377,8 +384,9 @@ int hpadi_net_pairs(hpadi_varcoef V, hpadi_plan precond, const double* b, int ld
 
 namespace hpadi_host {
 
-int net_correct(hpadi_net N, hpadi_varcoef_s* V, const double* r, double* z, bool* applied) {
+int net_correct(hpadi_net N, hpadi_varcoef_s* V, const double* r, double* z, int iter, bool* applied) {
     *applied = false;
+    if (iter % N->period != 0) return HPADI_OK;  // corrections at iterations 0, period, 2 period, ...
     hipStream_t st = V->stream;
     const long n = (long)V->Nx * V->Ny;
     int rc = ensure_slots(V);

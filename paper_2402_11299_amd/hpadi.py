@@ -86,6 +86,7 @@ SIGNATURES = {
     "hpadi_net_get_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
     "hpadi_net_set_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
     "hpadi_net_set_damping": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "hpadi_net_set_period": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hpadi_net_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p]),
     "hpadi_net_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -497,6 +498,10 @@ class Net:
     def set_damping(self, omega):
         """0: energy-optimal combination of z and the correction; omega > 0: z + omega c."""
         check(lib().hpadi_net_set_damping(self.handle, float(omega)), "hpadi_net_set_damping")
+
+    def set_period(self, period):
+        """Correct at every period-th Krylov iteration only (1: every iteration)."""
+        check(lib().hpadi_net_set_period(self.handle, int(period)), "hpadi_net_set_period")
 
     def forward(self, x):
         import torch

@@ -177,6 +177,13 @@ def test_learned_fcg_small(hp):
     assert std.status == hp.HPADI_OK and trd <= 1e-10 * (1 + 1e-3) and std.corrections == std.iters
     with pytest.raises(hp.HpadiError):
         net.set_damping(-1.0)
+    # correction at every second iteration only (iterations 0, 2, 4, ...)
+    net.set_period(2)
+    xe, ste, _ = vc.solve(b, pre, tol=1e-10, maxit=300, truncation=1, net=net)
+    tre = np.linalg.norm(bh - op.apply(xe.cpu().numpy())) / np.linalg.norm(bh)
+    assert ste.status == hp.HPADI_OK and tre <= 1e-10 * (1 + 1e-3) and ste.corrections == (ste.iters + 1) // 2
+    with pytest.raises(hp.HpadiError):
+        net.set_period(0)
     net.close()
     pre.close()
     vc.close()
