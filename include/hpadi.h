@@ -126,7 +126,10 @@ int hpadi_shifts(const double iv[4], double tol, int J_in, int* J, double* p, do
  * K_y + (omega2/2 + p_j) M_y and of M_y, computed on the GPU in FP64 (plus
  * FP32 copies in MIXED mode).  hip_stream: a hipStream_t or NULL.  The
  * operators are copied; they may be destroyed afterwards.  Synchronises the
- * stream.  ENOTSPD if a factorisation fails, ESINGULAR / EINTERVAL as above. */
+ * stream.  ENOTSPD if a factorisation fails, ESINGULAR / EINTERVAL as above.
+ * EINVAL for p > 129 or more than 65 hats on an axis (n > 64 elements with
+ * Dirichlet conditions, n > 64 with Neumann): the hat block of a line is solved
+ * by one 64-lane wavefront. */
 int hpadi_plan_create(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,
                       const double* interval, void* hip_stream, hpadi_plan* out);
 int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,

@@ -30,6 +30,10 @@ using hpadi::FactorLayout;
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+// The hat block of a line is solved by one wavefront (64 lanes, the last also taking a
+// 65th hat), so plans take at most 65 hats per axis: n <= 64 (Dirichlet), n <= 64
+// (Neumann, n + 1 hats).
+constexpr int kMaxHats = 65;
 
 // Bubble blocks on the reference element, scaled by delta (App. A, eq. app:1):
 double k_bub(int m) { return 4.0 / (2.0 * m + 3.0); }                                      // K (m,m) * delta
@@ -1109,7 +1113,7 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
         return HPADI_EINVAL;
     if (omega2 < 0.0 || ((x->bc == HPADI_NEUMANN || y->bc == HPADI_NEUMANN) && !(omega2 > 0.0)))
         return HPADI_ESINGULAR;
-    if (x->p / 2 > 64 || y->p / 2 > 64) return HPADI_EINVAL;
+    if (x->p / 2 > 64 || y->p / 2 > 64 || x->nh > kMaxHats || y->nh > kMaxHats) return HPADI_EINVAL;
     hpadi_plan_s* P = new (std::nothrow) hpadi_plan_s;
     if (!P) return HPADI_ENOMEM;
     if (opts) P->opt = *opts;
@@ -1345,8 +1349,14 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
 int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, const double* omega2, double tol,
                        const double* const* G, const int* ldg, double* const* U, const int* ldu, int autotune,
                        int nstreams, void* hip_stream, hpadi_batch* out) {
-    if (count < 1 || !xs || !ys || !omega2 || !G || !ldg || !U || !ldu || !out || !(tol > 0.0)) return HPADI_EINVAL;
+    if (count < 1 || !xs || !ys || !omega2 || !G || !ldg || !U || !ldu || !out || !(tol > 0.0 && tol < 1.0))
+        return HPADI_EINVAL;
     *out = nullptr;
+    // every instance is checked before the first HIP call
+    for (int i = 0; i < count; ++i)
+        if (!xs[i] || !ys[i] || !G[i] || !U[i] || ldg[i] < ys[i]->N || ldu[i] < ys[i]->N ||
+            xs[i]->nh > kMaxHats || ys[i]->nh > kMaxHats)
+            return HPADI_EINVAL;
     hpadi_batch_s* B = new (std::nothrow) hpadi_batch_s();
     if (!B) return HPADI_ENOMEM;
     B->count = count;
@@ -1361,11 +1371,6 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         B->own_origin = true;
     }
     (void)nstreams;
-    for (int i = 0; i < count; ++i)
-        if (!xs[i] || !ys[i]) {
-            delete B;
-            return HPADI_EINVAL;
-        }
     // autotuner: lines per workgroup (4 or 8) per distinct (n_x, p_x, n_y, p_y, bc), by timing
     // one fixed-schedule solve of each candidate on the instance's own data
     std::vector<std::pair<std::vector<int>, int>> tuned;

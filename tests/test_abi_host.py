@@ -112,6 +112,36 @@ def test_error_codes(hp):
     assert "tolerance" in hp.hpadi_strerror(hp.HPADI_ENOCONV)
 
 
+def test_size_limits_are_einval_before_any_gpu_call(hp):
+    """Plans with more than 65 hats on an axis, and batches with a missing array or a short
+    leading dimension, are rejected with EINVAL before the first HIP call (so on a host
+    without a GPU too)."""
+    import ctypes
+    big = hp.Op1D(65, 4, 0, 1, "dirichlet")     # 64 hats: accepted by the size check
+    bigger = hp.Op1D(66, 4, 0, 1, "neumann")    # 67 hats
+    small = hp.Op1D(4, 8, 0, 1, "dirichlet")
+    out = ctypes.c_void_p()
+    L = hp.lib()
+    assert L.hpadi_plan_create_ex(bigger.handle, small.handle, 1.0, 1e-6, hp.HPADI_FP64, None, None, None,
+                                  ctypes.byref(out)) == hp.HPADI_EINVAL
+    assert L.hpadi_plan_create_ex(small.handle, hp.Op1D(80, 4).handle, 1.0, 1e-6, hp.HPADI_FP64, None, None,
+                                  None, ctypes.byref(out)) == hp.HPADI_EINVAL
+    assert not out.value
+    del big
+    # batch: one good instance and one with a null U, or with ldu < N_y
+    xs = (ctypes.c_void_p * 2)(small.handle, small.handle)
+    w2 = (ctypes.c_double * 2)(1.0, 1.0)
+    fake = ctypes.c_void_p(4096)  # never dereferenced: validation fails first
+    for U1, ld1 in ((None, small.N), (fake, small.N - 1)):
+        G = (ctypes.c_void_p * 2)(fake, fake)
+        U = (ctypes.c_void_p * 2)(fake, U1)
+        ldg = (ctypes.c_int * 2)(small.N, small.N)
+        ldu = (ctypes.c_int * 2)(small.N, ld1)
+        b = ctypes.c_void_p()
+        rc = L.hpadi_batch_create(2, xs, xs, w2, 1e-10, G, ldg, U, ldu, 0, 0, None, ctypes.byref(b))
+        assert rc == hp.HPADI_EINVAL and not b.value
+
+
 def test_struct_layouts_match_the_header(hp):
     """The ctypes mirrors of hpadi_options and hpadi_stats have the layout the library's
     static_asserts fix (size and the offset of the last field added)."""
