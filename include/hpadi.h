@@ -154,6 +154,17 @@ int hpadi_plan_export_factor(hpadi_plan plan, int j, int axis, double* buf, size
  * N_x x N_y (ldg), both FP64 device memory. */
 int hpadi_load(hpadi_plan plan, const double* F_dev, int ldf, double* G_dev, int ldg);
 
+/* hpadi_load for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same G, computed in
+ * column blocks through a fixed 16 MiB scratch array that every GPU the library runs
+ * on holds until the process ends; no hipMalloc, hipFree or allocating library call.
+ * hpadi_load instead allocates an Nleg_x x N_y intermediate on its first call.
+ * Limit: Nleg_x <= 32768 (a block must hold at least 64 columns), else EINVAL.
+ * All calls on one GPU share its scratch: calls that overlap in time on one GPU
+ * (different streams, or host threads) race and must be serialised by the caller.
+ * Stream-ordered on the plan's stream; the device is the one current at the call. */
+int hpadi_load_noalloc(hpadi_plan plan, const double* F_dev, int ldf, double* G_dev, int ldg);
+
 /* Solve A_Y^x U M^y + M^x U A_Y^y = G (Alg. 2).  G_dev and U_dev are FP64
  * N_x x N_y device arrays.  FP64: J ADI iterations in FP64 (relative error
  * <= tol in the norm of the ADI lemma, Sec. 5.1).  MIXED: iterative

@@ -1234,6 +1234,25 @@ int hpadi_load(hpadi_plan P, const double* F, int ldf, double* G, int ldg) {
                : HPADI_EHIP;
 }
 
+int hpadi_load_noalloc(hpadi_plan P, const double* F, int ldf, double* G, int ldg) {
+    if (!P || !F || !G || ldf < P->dy.op.Nleg || ldg < P->dy.op.N) return HPADI_EINVAL;
+    // column blocks of w columns: the intermediate of one block, Nleg_x x w doubles, fills
+    // at most the fixed scratch
+    const long nleg = P->dx.op.Nleg;
+    long w = hpadi::kLoadScratchWords / nleg / 64 * 64;
+    if (w < 64) return HPADI_EINVAL;
+    if (w > P->dy.op.N) w = P->dy.op.N;
+    double* H = nullptr;
+    if (hpadi::load_scratch(&H) != hipSuccess) return HPADI_EHIP;
+    for (long j0 = 0; j0 < P->dy.op.N; j0 += w) {
+        const int nc = (int)std::min<long>(w, P->dy.op.N - j0);
+        if (hpadi::launch_load_cols(P->dx.dev, P->dy.dev, F, ldf, H, w, G, ldg, (int)j0, nc, P->stream) !=
+            hipSuccess)
+            return HPADI_EHIP;
+    }
+    return HPADI_OK;
+}
+
 int hpadi_apply(hpadi_plan P, const double* U, int ldu, double* Y, int ldy) {
     if (!P || !U || !Y || ldu < P->dy.op.N || ldy < P->dy.op.N) return HPADI_EINVAL;
     int rc = ensure_fp64_work(P);

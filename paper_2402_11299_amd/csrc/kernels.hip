@@ -13,6 +13,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace hpadi {
@@ -298,22 +300,22 @@ __device__ __forceinline__ double gather_load(const DimDev& d, const double* f, 
     return c0 * f[(long)(m * n + e) * sp] + c2 * f[(long)((m + 2) * n + e) * sp];
 }
 
-// H[i][j] = (T_y F[i, :])[j], i < Nleg_x.
+// H[i][j - j0] = (T_y F[i, :])[j] for the columns j0 <= j < j0 + ncols, i < Nleg_x.
 __global__ void __launch_bounds__(256) load_rows(DimDev dy, const double* F, long ldf, double* H, long ldh,
-                                                 int nrows) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+                                                 int nrows, int j0, int ncols) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
-    if (j >= dy.N || i >= nrows) return;
-    H[(long)i * ldh + j] = gather_load(dy, F + (long)i * ldf, 1, j);
+    if (jj >= ncols || i >= nrows) return;
+    H[(long)i * ldh + jj] = gather_load(dy, F + (long)i * ldf, 1, j0 + jj);
 }
 
-// G[i][j] = (T_x H[:, j])[i].
+// G[i][j0 + jj] = (T_x H[:, jj])[i], jj < ncols.
 __global__ void __launch_bounds__(256) load_cols(DimDev dx, const double* H, long ldh, double* G, long ldg,
-                                                 int ncols) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+                                                 int j0, int ncols) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
-    if (j >= ncols || i >= dx.N) return;
-    G[(long)i * ldg + j] = gather_load(dx, H + j, ldh, i);
+    if (jj >= ncols || i >= dx.N) return;
+    G[(long)i * ldg + j0 + jj] = gather_load(dx, H + jj, ldh, i);
 }
 
 __global__ void __launch_bounds__(256) convert_kernel(const double* src, long lds, float* dst, long ldd,
@@ -370,11 +372,47 @@ hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s) {
 
 hipError_t launch_load(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H, long ldh, double* G,
                        long ldg, hipStream_t s) {
-    hipLaunchKernelGGL(load_rows, grid2(dy.N, dx.Nleg), dim3(256), 0, s, dy, F, ldf, H, ldh, dx.Nleg);
+    return launch_load_cols(dx, dy, F, ldf, H, ldh, G, ldg, 0, dy.N, s);
+}
+
+hipError_t launch_load_cols(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H, long ldh,
+                            double* G, long ldg, int j0, int ncols, hipStream_t s) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(load_rows, grid2(ncols, dx.Nleg), dim3(256), 0, s, dy, F, ldf, H, ldh, dx.Nleg, j0, ncols);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(load_cols, grid2(dy.N, dx.N), dim3(256), 0, s, dx, H, ldh, G, ldg, dy.N);
+    hipLaunchKernelGGL(load_cols, grid2(ncols, dx.N), dim3(256), 0, s, dx, H, ldh, G, ldg, j0, ncols);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch for callers that cannot allocate: one array per device, holding a
+// column block of the intermediate H = F T_y^T of the load.  In host code the name
+// `scratch` is only a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+namespace {
+__device__ __align__(256) double scratch[kLoadScratchWords];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t load_scratch(double** out) {
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_convert_f64_f32(const double* src, long ld_src, float* dst, long ld_dst, int rows, int cols,

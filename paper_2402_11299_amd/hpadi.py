@@ -62,6 +62,8 @@ SIGNATURES = {
     "hpadi_plan_export_factor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_double_p,
                                                 ctypes.c_size_t]),
     "hpadi_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "hpadi_load_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_int]),
     "hpadi_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                    ctypes.POINTER(hpadi_stats)]),
     "hpadi_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
@@ -243,6 +245,12 @@ def hpadi_load(plan, F, G):
     fp, ldf = _tptr(F)
     gp, ldg = _tptr(G)
     check(lib().hpadi_load(plan, fp, ldf, gp, ldg), "hpadi_load")
+
+
+def hpadi_load_noalloc(plan, F, G):
+    fp, ldf = _tptr(F)
+    gp, ldg = _tptr(G)
+    check(lib().hpadi_load_noalloc(plan, fp, ldf, gp, ldg), "hpadi_load_noalloc")
 
 
 def hpadi_solve(plan, G, U, raise_on_noconv=True):
