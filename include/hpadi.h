@@ -171,8 +171,13 @@ int hpadi_load_noalloc(hpadi_plan plan, const double* F_dev, int ldf, double* G_
  * refinement on the FP64 residual, every round an ADI solve with the plan's
  * shift family (tolerance inner_tol): the first fp32_rounds rounds with FP32
  * storage between half-sweeps, the later ones in FP64; the solve stops after
- * an FP64 round once the lemma bound eps/(1-eps) ||delta|| / ||U|| (twice, for
- * the diagonal-mass norm used) is <= tol.  stats may be NULL.  ENOCONV if the
+ * an FP64 round once the bound of the ADI lemma (Sec. 5.1) on the relative error,
+ * f ||delta|| / (| ||U_old|| - ||delta|| | - f ||delta||) with f = eps/(1-eps),
+ * delta the round's correction and U_old the iterate before it, all in the
+ * lemma's norm ||V X L^T||_F (M^x = V^T V, M^y = L^T L), is <= tol
+ * (stats->est_rel_err).  The bound covers the truncation error of the ADI
+ * rounds; FP64 rounding adds its own, below 1e-11 relative in every test.
+ * stats may be NULL.  ENOCONV if the
  * round limit is reached (U holds the last iterate).  Synchronises the stream
  * in MIXED mode (one scalar read-back per FP64 round). */
 int hpadi_solve(hpadi_plan plan, const double* G_dev, int ldg, double* U_dev, int ldu,

@@ -10,6 +10,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -683,9 +684,8 @@ hpadi::SweepArgs adi_col_args(const hpadi_plan_s* P, const ShiftFamily& F, int j
     c.tau = j + 1 == F.J ? 0.0 : P->omega2 / 2.0 - F.P[j + 1];
     return c;
 }
-// Arguments of the final mass solve U (+)= L^{-1} w; norms: accumulate the weighted
-// squares of the correction and of the new U into P->acc[0..1].
-hpadi::SweepArgs final_args(const hpadi_plan_s* P, double* U, long ldu, bool accumulate, bool norms) {
+// Arguments of the final mass solve U (+)= L^{-1} w.
+hpadi::SweepArgs final_args(const hpadi_plan_s* P, double* U, long ldu, bool accumulate) {
     hpadi::SweepArgs f = sweep_args(P, P->first(), false, P->first().J);
     f.in = P->Wk;
     f.lin = P->lint;
@@ -693,8 +693,6 @@ hpadi::SweepArgs final_args(const hpadi_plan_s* P, double* U, long ldu, bool acc
     f.lout = user_layout(P, ldu);
     if ((double)ldu * P->dx.op.N >= 536870912.0) f.idx32 = 0;
     f.accumulate = accumulate ? 1 : 0;
-    f.norm_acc = norms ? P->acc : nullptr;
-    f.wline = P->dx.dev.mdiag;
     return f;
 }
 
@@ -707,20 +705,45 @@ int transform_rhs(hpadi_plan_s* P, const double* R, long ldr, int ts) {
     return timed_sweep(P, true, transform_col_args(P), hpadi::SWEEP_TRANSFORM, 8, ts, 2, dofs * (8.0 + ts));
 }
 
+// Arguments of the last column pass of family F (the solve that ends the ADI loop);
+// norms: add the squared norm of the round's correction in the ADI lemma's norm,
+// ||V delta L^T||_F^2, to P->acc[0].
+hpadi::SweepArgs last_col_args(const hpadi_plan_s* P, const ShiftFamily& F, bool norms) {
+    hpadi::SweepArgs c = adi_col_args(P, F, F.J - 1);
+    c.norm_acc = norms ? P->acc : nullptr;
+    return c;
+}
+
 // Alg. 2 solve loop in balanced coordinates with the shifts of family F, from G~ (in
-// P->Gt) to U (user layout): U = u or U += u (accumulate); norms as in final_args.
+// P->Gt) to U (user layout): U = u or U += u (accumulate); norms as in last_col_args.
 int run_adi(hpadi_plan_s* P, const ShiftFamily& F, int ts, double* U, long ldu, bool accumulate, bool norms) {
     const double dofs = (double)P->dx.op.N * P->dy.op.N;
     for (int j = 0; j < F.J; ++j) {
         int rc = timed_sweep(P, false, adi_row_args(P, F, j), hpadi::SWEEP_FULL, ts, ts, 1, dofs * 3.0 * ts);
         if (rc != HPADI_OK) return rc;
         const bool last = j + 1 == F.J;
-        rc = timed_sweep(P, true, adi_col_args(P, F, j), last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts,
-                         last ? 2 : 0, dofs * (last ? 2.0 : 3.0) * ts);
+        rc = timed_sweep(P, true, last ? last_col_args(P, F, norms) : adi_col_args(P, F, j),
+                         last ? hpadi::SWEEP_SOLVE : hpadi::SWEEP_FULL, ts, ts, last ? 2 : 0,
+                         dofs * (last ? 2.0 : 3.0) * ts);
         if (rc != HPADI_OK) return rc;
     }
-    return timed_sweep(P, false, final_args(P, U, ldu, accumulate, norms), hpadi::SWEEP_FINAL, ts, 8, 2,
+    return timed_sweep(P, false, final_args(P, U, ldu, accumulate), hpadi::SWEEP_FINAL, ts, 8, 2,
                        dofs * (ts + (accumulate ? 16.0 : 8.0)));
+}
+
+// Error bound of the ADI lemma (Sec. 5.1) after a refinement round whose shift family
+// has tolerance eps: with e the error before the round and delta its correction,
+// ||e - delta|| <= eps ||e|| gives ||U* - U_new|| <= f ||delta||, f = eps / (1 - eps);
+// and ||U*|| >= ||U_new|| - f ||delta|| >= | ||U_old|| - ||delta|| | - f ||delta||.
+// d2 = ||delta||^2, u2 = ||U_old||^2, both in the lemma's norm ||V X L^T||_F.  Returns
+// the bound on ||U* - U_new|| / ||U*|| (infinity when the denominator is not positive).
+double lemma_bound(double eps, double d2, double u2) {
+    const double nd = std::sqrt(std::max(d2, 0.0)), nu = std::sqrt(std::max(u2, 0.0));
+    if (!std::isfinite(nd) || !std::isfinite(nu)) return std::numeric_limits<double>::infinity();
+    if (nd == 0.0) return 0.0;
+    const double f = eps / (1.0 - eps);
+    const double lo = std::fabs(nu - nd) - f * nd;
+    return lo > 0.0 ? f * nd / lo : std::numeric_limits<double>::infinity();
 }
 
 // T1 = U M_y, T2 = U A_y (row operators, FP64).
@@ -750,12 +773,13 @@ int ensure_fp64_work(hpadi_plan_s* P) {
     return HPADI_OK;
 }
 
-// r = G - A U in FP64 into P->R64 (norms accumulated into P->acc[2..3]).
+// r = G - A U in FP64 into P->R64; P->acc[2..3] get the diagonal-mass weighted squares
+// of r and G, P->acc[4] the squared norm of U in the ADI lemma's norm.
 int residual_into_r64(hpadi_plan_s* P, const double* G, long ldg, const double* U, long ldu) {
     hipStream_t s = P->stream;
     int rc = row_products(P, U, ldu);
     if (rc != HPADI_OK) return rc;
-    if (hpadi::launch_zero_f64(P->acc + 2, 2, 1, 2, s) != hipSuccess) return HPADI_EHIP;
+    if (hpadi::launch_zero_f64(P->acc + 2, 3, 1, 3, s) != hipSuccess) return HPADI_EHIP;
     hpadi::Residual r{};
     r.G = G;
     r.g_ld = ldg;
@@ -771,12 +795,15 @@ int residual_into_r64(hpadi_plan_s* P, const double* G, long ldg, const double* 
     r.ncols = P->dy.op.N;
     r.norm_acc = P->acc + 2;
     r.wcol = P->dy.dev.mdiag;
+    r.U = U;
+    r.u_ld = ldu;
     return hpadi::launch_residual(P->dx.dev, r, s) == hipSuccess ? HPADI_OK : HPADI_EHIP;
 }
 
 // A refinement schedule with a fixed number of rounds (nfp32 rounds with FP32 storage,
 // then nfp64 FP64 rounds) and no host synchronisation or memset node, so that it can be
-// captured into a graph.  P->acc[0..1] hold the norms of the last round's correction
+// captured into a graph.  P->acc[0] and P->acc[4] hold the squared norms of the last
+// round's correction and of U before it (the inputs of lemma_bound)
 // and of U for the error bound.  Work arrays must already exist.
 int enqueue_fixed_solve(hpadi_plan_s* P, const double* G, long ldg, double* U, long ldu, int nfp32, int nfp64) {
     hipStream_t s = P->stream;
@@ -785,7 +812,8 @@ int enqueue_fixed_solve(hpadi_plan_s* P, const double* G, long ldg, double* U, l
         const int ts = k <= nfp32 ? 4 : 8;
         int rc;
         if (k > 1 && (rc = residual_into_r64(P, G, ldg, U, ldu)) != HPADI_OK) return rc;
-        if (hpadi::launch_zero_f64(P->acc, 2, 1, 2, s) != hipSuccess) return HPADI_EHIP;
+        // round 1 starts from U = 0
+        if (hpadi::launch_zero_f64(P->acc, k == 1 ? 5 : 1, 1, k == 1 ? 5 : 1, s) != hipSuccess) return HPADI_EHIP;
         if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
         // the first round writes U (no zeroing pass), later rounds add to it; FP32 rounds
         // take the first shift family, FP64 rounds the refinement family
@@ -1294,13 +1322,12 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
         // FP64, where the ADI lemma bounds the error of the round: with e the error before
         // the round and delta its correction, ||e - delta|| <= eps ||e|| and ||e|| <= ||delta||
         // / (1 - eps), so ||U* - U|| <= eps / (1 - eps) ||delta|| (eps: tolerance of the
-        // shift family of the round).  Norms are diagonal-mass weighted; kNormSafety covers
-        // the ratio of that norm to the L2 norm.  FP32 rounds have no such bound (their
-        // rounding floor depends on the spectrum of the residual) and never end the solve.
-        // FP32 rounds take the first shift family, FP64 rounds the refinement family.
+        // shift family of the round), all in the lemma's norm (lemma_bound).  FP32 rounds
+        // have no such bound (their rounding floor depends on the spectrum of the residual)
+        // and never end the solve.  FP32 rounds take the first shift family, FP64 rounds the
+        // refinement family.
         if ((rc = ensure_fp64_work(P)) != HPADI_OK) return rc;
         if (!P->R64 && dmalloc(&P->R64, (size_t)Nx * P->ldw) != hipSuccess) return HPADI_ENOMEM;
-        constexpr double kNormSafety = 2.0;
         double est = 1.0;
         const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
         int k = 0;
@@ -1310,7 +1337,8 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
             const int ts = fp32 ? 4 : 8;
             const ShiftFamily& F = fp32 ? P->first() : P->refine();
             const double eps = F.eps;
-            if (hipMemsetAsync(P->acc, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
+            // round 1 starts from U = 0 (acc[4], the norm of U before the round, stays 0)
+            if (hpadi::launch_zero_f64(P->acc, k == 1 ? 5 : 1, 1, k == 1 ? 5 : 1, s) != hipSuccess) return HPADI_EHIP;
             if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
             // the first round writes U, later rounds add their correction to it
             if ((rc = run_adi(P, F, ts, U, ldu, k > 1, true)) != HPADI_OK) return rc;
@@ -1318,17 +1346,15 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
             if (fp32) st.fp32_rounds++;
             const bool decide = P->opt.fixed_rounds <= 0 && !fp32;
             if (decide || k == maxr) {
-                if (hipMemcpyAsync(P->acc_host, P->acc, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                if (hipMemcpyAsync(P->acc_host, P->acc, 5 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess)
                     return HPADI_EHIP;
-                const double nd = std::sqrt(std::max(P->acc_host[0], 0.0));
-                const double nu = std::sqrt(std::max(P->acc_host[1], 0.0));
                 if (k > 1) {
                     const double gnorm = std::sqrt(std::max(P->acc_host[3], 0.0));
                     st.res_rel = gnorm > 0 ? std::sqrt(std::max(P->acc_host[2], 0.0)) / gnorm : 0.0;
                 }
-                est = fp32 ? 1.0 : (nu > 0 ? kNormSafety * eps / (1.0 - eps) * nd / nu : 0.0);
-                if (!std::isfinite(est)) break;
+                est = fp32 ? 1.0 : lemma_bound(eps, P->acc_host[0], P->acc_host[4]);
+                if (std::isnan(P->acc_host[0]) || std::isnan(P->acc_host[4])) break;
                 if (decide && est <= P->tol) {
                     done = true;
                     break;
@@ -1336,24 +1362,7 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
                 if (k == maxr) break;
             }
             // r = G - A U in FP64
-            if ((rc = row_products(P, U, ldu)) != HPADI_OK) return rc;
-            if (hipMemsetAsync(P->acc + 2, 0, 2 * sizeof(double), s) != hipSuccess) return HPADI_EHIP;
-            hpadi::Residual r{};
-            r.G = G;
-            r.g_ld = ldg;
-            r.T1 = P->T1;
-            r.T2 = P->T2;
-            r.t_ld = P->ldw;
-            r.r64 = P->R64;
-            r.r64_ld = P->ldw;
-            r.ax_k = 1.0;
-            r.ax_t = P->omega2 / 2.0;
-            r.alpha = 1.0;
-            r.beta = -1.0;
-            r.ncols = Ny;
-            r.norm_acc = P->acc + 2;
-            r.wcol = P->dy.dev.mdiag;
-            if (hpadi::launch_residual(P->dx.dev, r, s) != hipSuccess) return HPADI_EHIP;
+            if ((rc = residual_into_r64(P, G, ldg, U, ldu)) != HPADI_OK) return rc;
         }
         if (k > maxr) k = maxr;
         st.rounds = k;
@@ -1528,7 +1537,8 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
                 const ShiftFamily& F = fam(P);
                 if (jj >= F.J) continue;
                 rows.push_back({i, adi_row_args(P, F, jj)});
-                (jj + 1 == F.J ? last : cols).push_back({i, adi_col_args(P, F, jj)});
+                if (jj + 1 == F.J) last.push_back({i, last_col_args(P, F, true)});
+                else cols.push_back({i, adi_col_args(P, F, jj)});
             }
             add_sweeps(steps, table, B->plans, rows, hpadi::SWEEP_FULL, ts, ts, false);
             seal();
@@ -1537,7 +1547,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
             seal();
         }
         items.clear();
-        for (int i = 0; i < count; ++i) items.push_back({i, final_args(B->plans[i], U[i], ldu[i], round > 1, true)});
+        for (int i = 0; i < count; ++i) items.push_back({i, final_args(B->plans[i], U[i], ldu[i], round > 1)});
         add_sweeps(steps, table, B->plans, items, hpadi::SWEEP_FINAL, ts, 8, false);
         seal();
     }
@@ -1622,27 +1632,23 @@ int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
         hipStreamSynchronize(B->origin) != hipSuccess)
         return HPADI_EHIP;
     // lemma bound of the FP64 round; instances above the tolerance get further FP64 rounds
-    constexpr double kNormSafety = 2.0;
     int extra = 0, status = HPADI_OK;
     for (int i = 0; i < B->count; ++i) {
         hpadi_plan_s* P = B->plans[i];
         const double eps = P->refine().eps;
-        double nd = std::sqrt(std::max(B->acc_host[2 * i], 0.0)), nu = std::sqrt(std::max(B->acc_host[2 * i + 1], 0.0));
-        double est = nu > 0 ? kNormSafety * eps / (1.0 - eps) * nd / nu : 0.0;
+        double est = lemma_bound(eps, B->acc_host[2 * i], B->acc_host[2 * i + 1]);
         int rounds = 2;
         while (est > B->tol && rounds < P->opt.max_rounds) {
             int rc = residual_into_r64(P, B->G[i], B->ldg[i], B->U[i], B->ldu[i]);
-            if (rc == HPADI_OK && hpadi::launch_zero_f64(P->acc, 2, 1, 2, P->stream) != hipSuccess) rc = HPADI_EHIP;
+            if (rc == HPADI_OK && hpadi::launch_zero_f64(P->acc, 1, 1, 1, P->stream) != hipSuccess) rc = HPADI_EHIP;
             if (rc == HPADI_OK) rc = transform_rhs(P, P->R64, P->ldw, 8);
             if (rc == HPADI_OK) rc = run_adi(P, P->refine(), 8, B->U[i], B->ldu[i], true, true);
             if (rc == HPADI_OK &&
-                (hipMemcpyAsync(P->acc_host, P->acc, 2 * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
+                (hipMemcpyAsync(P->acc_host, P->acc, 5 * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
                  hipStreamSynchronize(P->stream) != hipSuccess))
                 rc = HPADI_EHIP;
             if (rc != HPADI_OK) return rc;
-            nd = std::sqrt(std::max(P->acc_host[0], 0.0));
-            nu = std::sqrt(std::max(P->acc_host[1], 0.0));
-            est = nu > 0 ? kNormSafety * eps / (1.0 - eps) * nd / nu : 0.0;
+            est = lemma_bound(eps, P->acc_host[0], P->acc_host[4]);
             ++rounds;
             ++extra;
         }

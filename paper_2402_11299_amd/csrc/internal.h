@@ -86,8 +86,7 @@ struct SweepArgs {
     int lpb;                        // lines per workgroup: the panel width of the internal layout (4 or 8)
     int idx32;                      // every array addressed by this sweep has < 2^31 entries
     int xcd_group;                  // row passes: workgroups sharing 128-byte lines (1 = none)
-    double* norm_acc;               // FINAL: [sum w u^2, sum w U^2] or NULL
-    const double* wline;            // FINAL: weight per line
+    double* norm_acc;               // SOLVE (column pass): adds |Lm w|^2 over the lines, or NULL
 };
 hipError_t launch_sweep(const DimDev& d, const SweepArgs& a, int mode, int tin, int tout, bool column,
                         hipStream_t s);
@@ -155,8 +154,10 @@ struct Residual {
     double ax_k, ax_t;   // A_x = ax_k K + ax_t M
     double alpha, beta;  // r = alpha G + beta (A_x T1 + M_x T2)
     int ncols;
-    double* norm_acc;    // [sum w r^2, sum w G^2] or NULL
+    double* norm_acc;    // [sum w r^2, sum w G^2, <U, M_x T1>] or NULL
     const double* wcol;  // diag of M^y (weights along columns)
+    const double* U; long u_ld;  // with T1 = U M_y: <U, M_x U M_y>, the squared norm of U in
+                                 // the ADI lemma's norm, into norm_acc[2] (U may be NULL)
 };
 hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s);
 

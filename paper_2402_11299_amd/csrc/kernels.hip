@@ -223,25 +223,27 @@ __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     // flight at once.  The weighted sums of squares are reduced per block (one atomic
     // pair per block).
     constexpr int RU = 4;
-    __shared__ double red[2][4];
+    __shared__ double red[3][4];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int rpb = (dx.N + gridDim.y - 1) / gridDim.y;
     const int ibeg = blockIdx.y * rpb, iend = min(dx.N, ibeg + rpb);
-    double sr = 0.0, sg = 0.0;
+    double sr = 0.0, sg = 0.0, su = 0.0;
     if (j < a.ncols) {
         for (int i0 = ibeg; i0 < iend; i0 += RU) {
-            double rv[RU], gv[RU];
+            double rv[RU], gv[RU], uv[RU];
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
                 const int i = i0 + u;
                 rv[u] = 0.0;
                 gv[u] = 0.0;
+                uv[u] = 0.0;
                 if (i < iend) {
                     double K1, M1, K2, M2;
                     gather_km(dx, a.T1 + j, a.t_ld, i, K1, M1);
                     gather_km(dx, a.T2 + j, a.t_ld, i, K2, M2);
                     gv[u] = a.G ? a.G[(long)i * a.g_ld + j] : 0.0;
                     rv[u] = a.alpha * gv[u] + a.beta * (a.ax_k * K1 + a.ax_t * M1 + M2);
+                    if (a.U) uv[u] = a.U[(long)i * a.u_ld + j] * M1;
                 }
             }
 #pragma unroll
@@ -255,6 +257,7 @@ __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
                     const double w = dx.mdiag[i] * a.wcol[j];
                     sr += w * r * r;
                     sg += w * g * g;
+                    su += uv[u];
                 }
             }
         }
@@ -262,15 +265,18 @@ __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     if (a.norm_acc) {
         sr = wave_sum(sr);
         sg = wave_sum(sg);
+        su = wave_sum(su);
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             red[0][w] = sr;
             red[1][w] = sg;
+            red[2][w] = su;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             atomicAdd(a.norm_acc + 0, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
             atomicAdd(a.norm_acc + 1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+            if (a.U) atomicAdd(a.norm_acc + 2, red[2][0] + red[2][1] + red[2][2] + red[2][3]);
         }
     }
 }
@@ -433,8 +439,9 @@ namespace {
 __global__ void gather_acc_kernel(const double* const* accs, int count, double* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
+    // squared norms of the last correction and of U before it (lemma bound inputs)
     out[2 * i] = accs[i][0];
-    out[2 * i + 1] = accs[i][1];
+    out[2 * i + 1] = accs[i][4];
 }
 }  // namespace
 

@@ -227,6 +227,7 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
         }
         if (MODE == SWEEP_SOLVE) {
             TOUT* out = reinterpret_cast<TOUT*>(a.out);
+            double sq = 0.0;
             if (act) {
                 long oo = chain_off(a.lout, 0);
                 const long so = UNI ? chain_off(a.lout, 1) - oo : 0;
@@ -234,7 +235,25 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
                 for (int s = 0; s < CL; ++s)
                     if (s < len) out[UNI ? oo + s * so : chain_off(a.lout, s)] = (TOUT)y[s];
                 if (c < nh) out[IDX(a.lout, line, c)] = (TOUT)A[c];
+                if (a.norm_acc) {
+                    // |Lm w|^2 of this chain (and of hat c): the line's share of the squared
+                    // norm of the correction in the norm of the ADI error lemma
+#pragma unroll
+                    for (int s = 0; s < CL; ++s)
+                        if (s < len) {
+                            const int m = pi + 2 * s;
+                            double v = M_d(m) * y[s];
+                            if (s == 0) v += FM.cpl[4 * e + 2 * pi] * xl + FM.cpl[4 * e + 2 * pi + 1] * xr;
+                            else v += M_lnk(m) * y[s - 1];
+                            sq += v * v;
+                        }
+                    if (c < nh) {
+                        const double v = FM.d0[c] * A[c] + (c > 0 ? FM.link0[c] * A[c - 1] : 0.0);
+                        sq += v * v;
+                    }
+                }
             }
+            if (a.norm_acc) block_sum_atomic(sq, sm, a.norm_acc);
             return;
         }
         // ---- product v = (kappa K + tau M) x and u = Lm^{-T} v, fused (highest degree first)
@@ -356,13 +375,11 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
         __syncthreads();
         for_my_lines([&](int ll) { hat_forward(sA + ll * hs, FM, nh, lane); });
         __syncthreads();
-        double sdx = 0.0, su = 0.0;
         if (act) {
             double xl = 0.0, xr = 0.0;
             if (vhat(d.bc, n, e)) xl = A[hov(d.bc, e)];
             if (vhat(d.bc, n, e + 1)) xr = A[hov(d.bc, e + 1)];
             double* out = reinterpret_cast<double*>(a.out);
-            const double* w = d.mdiag;
             double prev = 0.0;
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
@@ -372,44 +389,13 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
                     if (s == 0) v -= FM.cpl[4 * e + 2 * pi] * xl + FM.cpl[4 * e + 2 * pi + 1] * xr;
                     else v -= M_lnk(m) * prev;
                     prev = v * M_inv(m);
-                    const int pos = nh + 2 * s * n + c;
                     const long o = chain_off(a.lout, s);
-                    const double u = a.accumulate ? out[o] + prev : prev;
-                    out[o] = u;
-                    sdx += w[pos] * prev * prev;
-                    su += w[pos] * u * u;
+                    out[o] = a.accumulate ? out[o] + prev : prev;
                 }
             }
             if (c < nh) {
                 const long o = IDX(a.lout, line, c);
-                const double dx = A[c];
-                const double u = a.accumulate ? out[o] + dx : dx;
-                out[o] = u;
-                sdx += w[c] * dx * dx;
-                su += w[c] * u * u;
-            }
-            if (a.norm_acc) {
-                const double wl = a.wline[line];
-                sdx *= wl;
-                su *= wl;
-            }
-        }
-        if (a.norm_acc) {
-            __syncthreads();
-            sm[2 * tid] = sdx;
-            sm[2 * tid + 1] = su;
-            __syncthreads();
-            for (int w2 = blockDim.x; w2 > 1; w2 = (w2 + 1) / 2) {
-                const int half = (w2 + 1) / 2;
-                if (tid + half < w2) {
-                    sm[2 * tid] += sm[2 * (tid + half)];
-                    sm[2 * tid + 1] += sm[2 * (tid + half) + 1];
-                }
-                __syncthreads();
-            }
-            if (tid == 0) {
-                atomicAdd(a.norm_acc + 0, sm[0]);
-                atomicAdd(a.norm_acc + 1, sm[1]);
+                out[o] = a.accumulate ? out[o] + A[c] : A[c];
             }
         }
     }
@@ -550,7 +536,9 @@ __global__ void pass_table_kernel(DimDev d, const double* facS, int stride, cons
         r[10] = -mlnk * minv;
         r[11] = -mlnk_up * minv;
         r[12] = minv * tau * de;
-        r[13] = md[m] * de;  // diagonal of M at degree m (weights of the norm estimates)
+        r[13] = md[m] * de;  // diagonal of M at degree m
+        r[14] = facM[fl.off_d + m * n];  // mass factor: diagonal and link to degree m - 2
+        r[15] = mlnk;
     }
 }
 }  // namespace

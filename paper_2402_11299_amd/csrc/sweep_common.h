@@ -111,6 +111,23 @@ __device__ __forceinline__ double head_coupling(const double* C, const double* h
 }
 
 
+// Adds the sum of v over the workgroup to *acc (one atomic per workgroup).  Every thread
+// of the workgroup calls it; red is LDS of at least blockDim.x / 64 doubles, free once
+// every thread has reached the call.
+__device__ __forceinline__ void block_sum_atomic(double v, double* red, double* acc) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        atomicAdd(acc, t);
+    }
+}
+
 size_t sweep_lds_bytes(const DimDev& d, int threads, int mode);
 
 }  // namespace sweep_detail

@@ -222,11 +222,31 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             H1[c] = y[0];
         }
         if (MODE == SWEEP_SOLVE) {
+            double sq = 0.0;
             if (act) {
                 TOUT* out = reinterpret_cast<TOUT*>(a.out);
                 store_chain(out, a.lout, [&](int s) { return y[s]; });
                 if (c < nh) out[IDX(a.lout, line, c)] = (TOUT)A[c];
+                if (a.norm_acc) {
+                    // |Lm w|^2 of this chain (and of hat c): the line's share of the squared
+                    // norm of the correction in the norm of the ADI error lemma
+                    double prev = 0.0;
+#pragma unroll
+                    for (int s = 0; s < CL; ++s) {
+                        const int m = pi + 2 * s;
+                        double v = PT(m, 14) * y[s];
+                        if (s == 0) v += FM.cpl[4 * e + 2 * pi] * xl + FM.cpl[4 * e + 2 * pi + 1] * xr;
+                        else v += PT(m, 15) * prev;
+                        sq += v * v;
+                        prev = y[s];
+                    }
+                    if (c < nh) {
+                        const double v = FM.d0[c] * A[c] + (c > 0 ? FM.link0[c] * A[c - 1] : 0.0);
+                        sq += v * v;
+                    }
+                }
             }
+            if (a.norm_acc) block_sum_atomic(sq, sm, a.norm_acc);
             return;
         }
         const double kap = a.kappa, tau = a.tau;
@@ -350,7 +370,6 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
         __syncthreads();
         for_my_lines([&](int ll) { hat_forward(sA + ll * hs, FM, nh, lane); });
         __syncthreads();
-        double sdx = 0.0, su = 0.0;
         if (act) {
             double xl = 0.0, xr = 0.0;
             if (vhat(d.bc, n, e)) xl = A[hov(d.bc, e)];
@@ -378,44 +397,11 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
                 const int m = pi + 2 * s;
                 if (s == 0) prev = (y[0] - FM.cpl[4 * e + 2 * pi] * xl - FM.cpl[4 * e + 2 * pi + 1] * xr) * PT(m, 9);
                 else prev = PT(m, 9) * y[s] + PT(m, 10) * prev;
-                if (s < CL - 1 || full) {
-                    const double u = uo[s] + prev;
-                    *reinterpret_cast<double*>(ob + o0 + (unsigned)s * st) = u;
-                    const double wm = PT(m, 13);
-                    sdx += wm * prev * prev;
-                    su += wm * u * u;
-                }
+                if (s < CL - 1 || full) *reinterpret_cast<double*>(ob + o0 + (unsigned)s * st) = uo[s] + prev;
             }
             if (c < nh) {
                 const long oh = IDX(a.lout, line, c);
-                const double dx = A[c];
-                const double u = a.accumulate ? out[oh] + dx : dx;
-                out[oh] = u;
-                sdx += d.mdiag[c] * dx * dx;
-                su += d.mdiag[c] * u * u;
-            }
-            if (a.norm_acc) {
-                const double wl = a.wline[line];
-                sdx *= wl;
-                su *= wl;
-            }
-        }
-        if (a.norm_acc) {
-            __syncthreads();
-            sm[2 * tid] = sdx;
-            sm[2 * tid + 1] = su;
-            __syncthreads();
-            for (int w2 = blockDim.x; w2 > 1; w2 = (w2 + 1) / 2) {
-                const int half = (w2 + 1) / 2;
-                if (tid + half < w2) {
-                    sm[2 * tid] += sm[2 * (tid + half)];
-                    sm[2 * tid + 1] += sm[2 * (tid + half) + 1];
-                }
-                __syncthreads();
-            }
-            if (tid == 0) {
-                atomicAdd(a.norm_acc + 0, sm[0]);
-                atomicAdd(a.norm_acc + 1, sm[1]);
+                out[oh] = a.accumulate ? out[oh] + A[c] : A[c];
             }
         }
     }

@@ -4,10 +4,11 @@ Neumann), in the launch configuration bench.py times.
 The exact discrete solution is known by construction (round trip): U0 is drawn,
 G0 = A_Y^x U0 M^y + M^x U0 A_Y^y is formed by the FP64 oracle, the GPU solves
 G0, and the relative L2 function error against U0 (the norm of the ADI lemma,
-Sec. 5.1) must meet the requested tolerance 1e-10.  Two draws: coefficients
+Sec. 5.1) must meet the requested tolerance 1e-10.  Three draws: coefficients
 decaying like (1+k)^-2 in the degree (the shape of a solution for the
-benchmark's right-hand sides) and flat N(0,1) coefficients (every mode equally
-excited, the hardest case for the refinement).
+benchmark's right-hand sides), flat N(0,1) coefficients (every mode equally
+excited) and coefficients on the highest degrees only (the hardest case for the
+refinement).  For mixed solves the stopping bound must also cover the true error.
 """
 import numpy as np
 import pytest
@@ -15,7 +16,7 @@ import pytest
 import workloads
 from oracle import adi as oadi
 from oracle import basis as obasis
-from tests.gpu_helpers import gpu_available
+from tests.gpu_helpers import ROUNDING_ALLOWANCE, gpu_available
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs an MI355X GPU")]
@@ -32,7 +33,7 @@ def hp():
 
 
 @pytest.mark.parametrize("cfg,prec", CASES, ids=lambda v: getattr(v, "name", v))
-@pytest.mark.parametrize("draw", ["decaying", "flat"])
+@pytest.mark.parametrize("draw", ["decaying", "flat", "highfreq"])
 def test_full_size_round_trip(hp, cfg, prec, draw):
     import torch
     print(f"full-size round trip {cfg.name} {prec} {draw}", flush=True)
@@ -40,6 +41,8 @@ def test_full_size_round_trip(hp, cfg, prec, draw):
     oy = obasis.assemble(obasis.make_basis(cfg.ny, cfg.py, cfg.ay, cfg.by, cfg.bc))
     if draw == "decaying":
         U0 = workloads.decaying_coefficients(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.bc, seed=cfg.seed + 100)
+    elif draw == "highfreq":
+        U0 = workloads.highfreq_coefficients(cfg.nx, cfg.px, cfg.ny, cfg.py, cfg.bc, seed=cfg.seed + 400)
     else:
         U0 = np.random.default_rng(cfg.seed + 200).standard_normal((ox.basis.N, oy.basis.N))
     G0 = oadi.apply_operator(ox, oy, cfg.omega2, U0)
@@ -51,6 +54,9 @@ def test_full_size_round_trip(hp, cfg, prec, draw):
     print(f"  rounds={st.rounds} J={st.J} est={st.est_rel_err:.2e} err={err:.2e}", flush=True)
     assert st.status == hp.HPADI_OK
     assert err <= cfg.tol
+    if prec == "mixed":
+        # the stopping bound (ADI lemma in its own norm) is sound
+        assert st.est_rel_err <= cfg.tol and err <= st.est_rel_err + ROUNDING_ALLOWANCE
     plan.close()
 
 

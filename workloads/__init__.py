@@ -72,6 +72,19 @@ def decaying_coefficients(nx: int, px: int, ny: int, py: int, bc: str, seed: int
     return Z * (1.0 + kx)[:, None] ** -2 * (1.0 + ky)[None, :] ** -2
 
 
+def highfreq_coefficients(nx: int, px: int, ny: int, py: int, bc: str, seed: int) -> np.ndarray:
+    """A random coefficient array concentrated on the highest degrees: N(0,1) entries where
+    either degree is at least p - 3, hats with alternating signs along each axis, and zero
+    elsewhere (round-trip tests of the error bound on rough solutions)."""
+    rng = np.random.default_rng(seed)
+    kx, ky = q_degrees(nx, px, bc), q_degrees(ny, py, bc)
+    Z = rng.standard_normal((kx.size, ky.size))
+    top = (kx[:, None] >= px - 3) | (ky[None, :] >= py - 3)
+    sx = np.where(kx == 1, (-1.0) ** np.arange(kx.size), 0.0)
+    sy = np.where(ky == 1, (-1.0) ** np.arange(ky.size), 0.0)
+    return np.where(top, Z, 0.0) + np.outer(sx, sy)
+
+
 # The problem families (uniform meshes, both axes share the BC):
 CFG_SMALL = Problem("poisson_n4_p8_dirichlet", 4, 8, 4, 8, 0.0, "dirichlet", 1e-12, 0)
 CFG_FP64_1K = Problem("screened_n32_p32_dirichlet_w2_10", 32, 32, 32, 32, 10.0, "dirichlet",
