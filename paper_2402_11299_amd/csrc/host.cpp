@@ -1132,6 +1132,40 @@ int build_family(hpadi_plan_s* P, const hpadi_op1d_s& x, const hpadi_op1d_s& y, 
     return ptables(P->dx, F.facx64, P->flx, tc, &F.ptabx);
 }
 
+// The shift family for an FP64 refinement round that follows one whose error bound was
+// `bound`: the round multiplies the error by at most eps / (1 - eps) (ADI lemma), so the
+// loosest family of the ladder 0.1, 0.03, 0.01, ... with eps <= 0.8 tol / bound suffices,
+// and costs fewer shifts than the first refinement family.  Ladder families are built
+// (factorised on the plan's stream) on first use.  *out = the family to use.
+int ladder_family(hpadi_plan_s* P, double bound, const ShiftFamily** out) {
+    *out = &P->refine();
+    const double want = 0.8 * P->tol / bound;
+    if (!(bound > 0.0) || !(want > P->refine().eps)) return HPADI_OK;
+    static const double rungs[] = {0.1, 0.03, 0.01, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5};
+    double eps = 0.0;
+    for (double r : rungs)
+        if (r <= want) {
+            eps = r;
+            break;
+        }
+    if (!(eps > P->refine().eps)) return HPADI_OK;
+    for (int i = 1; i < P->nfam; ++i)
+        if (P->fam[i].eps == eps) {
+            *out = &P->fam[i];
+            return HPADI_OK;
+        }
+    if (P->nfam >= hpadi_plan_s::kMaxFam) return HPADI_OK;
+    ShiftFamily& F = P->fam[P->nfam];
+    const int rc = build_family(P, P->dx.op, P->dy.op, eps, F);
+    if (rc != HPADI_OK) {
+        family_free(F);
+        return rc;
+    }
+    P->nfam++;
+    *out = &F;
+    return HPADI_OK;
+}
+
 int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,
                          const double* interval, void* hip_stream, const hpadi_options* opts, hpadi_plan* out) {
     if (!out) return HPADI_EINVAL;
@@ -1168,18 +1202,19 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     }
     if ((rc = make_dim(P->dx, *x)) != HPADI_OK || (rc = make_dim(P->dy, *y)) != HPADI_OK) { plan_free(P); return rc; }
     // FP64 plans: one family for tol.  Mixed plans: the FP32 rounds use inner_tol; the
-    // FP64 refinement rounds need only tol / (2 e), with e the error left by the FP32
-    // round, which follows inner_tol down to the FP32 rounding floor: a family for
-    // tol / (4 inner_tol) allows e up to twice inner_tol, and a further FP64 round
-    // covers a larger one.
+    // first FP64 refinement round needs eps <= tol / e (ADI lemma), e the error left by the
+    // FP32 round, which follows inner_tol down to the FP32 rounding floor: a family for
+    // tol / inner_tol meets tol after two rounds when e <= inner_tol (measured fastest at
+    // n = p = 64 against 1e-4 and 1e-3), and a later round takes a looser ladder family.
     const double eps0 = precision == HPADI_FP64 ? tol : std::max(P->opt.inner_tol, tol);
     if ((rc = build_family(P, *x, *y, eps0, P->fam[0])) != HPADI_OK) { plan_free(P); return rc; }
     if (precision == HPADI_MIXED) {
-        double eps1 = P->opt.refine_tol > 0.0 ? P->opt.refine_tol : tol / (4.0 * eps0);
+        double eps1 = P->opt.refine_tol > 0.0 ? P->opt.refine_tol : tol / eps0;
         eps1 = std::min(0.1, std::max(eps1, tol));
         if (eps1 != eps0) {
             if ((rc = build_family(P, *x, *y, eps1, P->fam[1])) != HPADI_OK) { plan_free(P); return rc; }
             P->nfam = 2;
+            P->iref = 1;
         }
     }
     // workspace: internal panel layout (8-column panels, hats padded to a multiple of 8)
@@ -1324,18 +1359,23 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
         // / (1 - eps), so ||U* - U|| <= eps / (1 - eps) ||delta|| (eps: tolerance of the
         // shift family of the round), all in the lemma's norm (lemma_bound).  FP32 rounds
         // have no such bound (their rounding floor depends on the spectrum of the residual)
-        // and never end the solve.  FP32 rounds take the first shift family, FP64 rounds the
-        // refinement family.
+        // and never end the solve.  FP32 rounds take the first shift family, the first FP64
+        // round the refinement family, later FP64 rounds the loosest family that the bound
+        // of the round before allows (ladder_family).
         if ((rc = ensure_fp64_work(P)) != HPADI_OK) return rc;
         if (!P->R64 && dmalloc(&P->R64, (size_t)Nx * P->ldw) != hipSuccess) return HPADI_ENOMEM;
-        double est = 1.0;
+        double est = 1.0, last_bound = 0.0;
         const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
         int k = 0;
         bool done = false;
         for (k = 1; k <= maxr; ++k) {
             const bool fp32 = k <= P->opt.fp32_rounds;
             const int ts = fp32 ? 4 : 8;
-            const ShiftFamily& F = fp32 ? P->first() : P->refine();
+            const ShiftFamily* Fp = fp32 ? &P->first() : &P->refine();
+            if (!fp32 && P->opt.fixed_rounds <= 0 && std::isfinite(last_bound) && last_bound > 0.0 &&
+                (rc = ladder_family(P, last_bound, &Fp)) != HPADI_OK)
+                return rc;
+            const ShiftFamily& F = *Fp;
             const double eps = F.eps;
             // round 1 starts from U = 0 (acc[4], the norm of U before the round, stays 0)
             if (hpadi::launch_zero_f64(P->acc, k == 1 ? 5 : 1, 1, k == 1 ? 5 : 1, s) != hipSuccess) return HPADI_EHIP;
@@ -1354,6 +1394,7 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
                     st.res_rel = gnorm > 0 ? std::sqrt(std::max(P->acc_host[2], 0.0)) / gnorm : 0.0;
                 }
                 est = fp32 ? 1.0 : lemma_bound(eps, P->acc_host[0], P->acc_host[4]);
+                if (!fp32) last_bound = est;
                 if (std::isnan(P->acc_host[0]) || std::isnan(P->acc_host[4])) break;
                 if (decide && est <= P->tol) {
                     done = true;
@@ -1411,11 +1452,11 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
     auto make_plan = [&](int i, int lw, hpadi_plan* pl) -> int {
         hpadi_options o{};
         o.lines_per_block = lw;
-        // one family (3e-6) for both rounds: the batch's small, rough instances leave FP32
-        // errors well above 3e-7, so a looser FP64 family would send many of them to a
-        // further round outside the graph
+        // FP32 round at 3e-6, FP64 round at 1e-6: the batch's small, rough instances leave
+        // FP32 errors well above 3e-7, and the FP64 family must take them to tol in one
+        // round, or they need a further round outside the graph
         o.inner_tol = 3e-6;
-        o.refine_tol = 3e-6;
+        o.refine_tol = 1e-6;
         int rc = hpadi_plan_create_ex(xs[i], ys[i], omega2[i], tol, HPADI_MIXED, nullptr, B->origin, &o, pl);
         if (rc != HPADI_OK) return rc;
         hpadi_plan_s* P = *pl;
@@ -1637,18 +1678,21 @@ int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
         hpadi_plan_s* P = B->plans[i];
         const double eps = P->refine().eps;
         double est = lemma_bound(eps, B->acc_host[2 * i], B->acc_host[2 * i + 1]);
-        int rounds = 2;
+        int rounds = 2, iters = P->first().J + P->refine().J;
         while (est > B->tol && rounds < P->opt.max_rounds) {
-            int rc = residual_into_r64(P, B->G[i], B->ldg[i], B->U[i], B->ldu[i]);
+            const ShiftFamily* F = &P->refine();
+            int rc = std::isfinite(est) ? ladder_family(P, est, &F) : HPADI_OK;
+            if (rc == HPADI_OK) rc = residual_into_r64(P, B->G[i], B->ldg[i], B->U[i], B->ldu[i]);
             if (rc == HPADI_OK && hpadi::launch_zero_f64(P->acc, 1, 1, 1, P->stream) != hipSuccess) rc = HPADI_EHIP;
             if (rc == HPADI_OK) rc = transform_rhs(P, P->R64, P->ldw, 8);
-            if (rc == HPADI_OK) rc = run_adi(P, P->refine(), 8, B->U[i], B->ldu[i], true, true);
+            if (rc == HPADI_OK) rc = run_adi(P, *F, 8, B->U[i], B->ldu[i], true, true);
             if (rc == HPADI_OK &&
                 (hipMemcpyAsync(P->acc_host, P->acc, 5 * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
                  hipStreamSynchronize(P->stream) != hipSuccess))
                 rc = HPADI_EHIP;
             if (rc != HPADI_OK) return rc;
-            est = lemma_bound(eps, P->acc_host[0], P->acc_host[4]);
+            est = lemma_bound(F->eps, P->acc_host[0], P->acc_host[4]);
+            iters += F->J;
             ++rounds;
             ++extra;
         }
@@ -1659,7 +1703,7 @@ int hpadi_batch_solve(hpadi_batch B, hpadi_stats* stats, int* n_extra) {
             st.J_refine = P->refine().J;
             st.rounds = rounds;
             st.fp32_rounds = 1;
-            st.iters = P->first().J + (rounds - 1) * P->refine().J;
+            st.iters = iters;
             st.status = est <= B->tol ? HPADI_OK : HPADI_ENOCONV;
             st.est_rel_err = est;
             for (int k = 0; k < 4; ++k) st.interval[k] = P->interval[k];

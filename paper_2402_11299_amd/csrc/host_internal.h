@@ -53,14 +53,17 @@ struct hpadi_plan_s {
     hpadi_options opt{};
     double interval[4] = {0, 0, 0, 0};
     // fam[0]: the family of an FP64 plan, or of the FP32 rounds of a mixed plan;
-    // fam[nfam - 1]: the family of the FP64 refinement rounds of a mixed plan
-    ShiftFamily fam[2];
+    // fam[iref]: the family of the first FP64 refinement round of a mixed plan; further
+    // (looser) families are built on first use for later rounds (ladder_family)
+    static constexpr int kMaxFam = 8;
+    ShiftFamily fam[kMaxFam];
     int nfam = 1;
+    int iref = 0;
     int lpb_col = 8, lpb_row = 8; // lines per workgroup of the column / row half-sweeps
     hipStream_t stream = nullptr;
     hpadi::FactorLayout flx{}, fly{};
     const ShiftFamily& first() const { return fam[0]; }
-    const ShiftFamily& refine() const { return fam[nfam - 1]; }
+    const ShiftFamily& refine() const { return fam[iref]; }
     // work arrays in the internal panel layout
     hpadi::Layout lint{};
     size_t nint = 0;              // elements per internal array

@@ -162,8 +162,9 @@ def test_mixed_error_bound_is_sound(hp, torch, nx, px, bc, w2, draw):
 @pytest.mark.parametrize("refine_tol", [0.0, 1e-8])
 def test_mixed_shift_families(hp, torch, refine_tol):
     """A mixed plan builds one shift family for its FP32 round (inner_tol, default 3e-7) and
-    one for its FP64 refinement rounds (default tol / (4 inner_tol)); both counts are those
-    of the Zolotarev formula for the plan's interval, and the solve meets the tolerance."""
+    one for its first FP64 refinement round (default tol / inner_tol); both counts are
+    those of the Zolotarev formula for the plan's interval, and the solve meets the
+    tolerance.  A third round would take a looser ladder family, never more shifts."""
     nx, px, bc, w2, tol = 8, 16, "dirichlet", 0.0, 1e-10
     x, y = hp.Op1D(nx, px, 0, 1, bc), hp.Op1D(nx, px, 0, 1, bc)
     ox = oracle_ops(nx, px, bc)
@@ -172,10 +173,10 @@ def test_mixed_shift_families(hp, torch, refine_tol):
     plan = hp.Plan(x, y, w2, tol, "mixed", options=opts)
     G = oadi.load(ox, ox, workloads.legendre_rhs(nx, px, nx, px, seed=4))
     U, st = plan.solve(torch.from_numpy(G).cuda())
-    eps1 = refine_tol if refine_tol > 0 else tol / (4 * 3e-7)
+    eps1 = refine_tol if refine_tol > 0 else tol / 3e-7
     assert st.J == hp.hpadi_shifts(plan.interval, 3e-7)[0] == plan.J
     assert st.J_refine == hp.hpadi_shifts(plan.interval, eps1)[0]
-    assert st.iters == st.J + (st.rounds - 1) * st.J_refine
+    assert st.J + st.J_refine <= st.iters <= st.J + (st.rounds - 1) * st.J_refine
     Uref = oadi.solve_fdm(ox, ox, w2, G, refine=2)
     err = oadi.rel_l2_error(U.cpu().numpy(), Uref, ox, ox)
     print("families", st.J, st.J_refine, "rounds", st.rounds, "err", err, flush=True)
