@@ -21,8 +21,9 @@
 // each wavefront reads LW lines x 64/LW consecutive positions: 256 bytes (FP32)
 // in contiguous runs of at least 64 bytes, in both sweep directions.  The hat block of each line (the Schur
 // complement of Alg. 1, n_h <= 65 unknowns) is solved by one wavefront per line
-// as parallel prefix/suffix scans of affine maps, with the hat factors staged in
-// LDS.
+// as one 64-lane prefix composition of affine maps built from DPP row shifts and
+// row broadcasts (the backward solve with its hats in reverse lane order), with the
+// hat factors staged in LDS.
 
 #include <hip/hip_runtime.h>
 

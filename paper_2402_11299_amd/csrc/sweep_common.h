@@ -30,55 +30,59 @@ struct HatF {
     double* cpl;    // 4n
 };
 
-// Suffix scan over lanes of affine maps z = a + b z_next (lane k composes with
-// lane k+1, k+2, ...): afterwards a = value of the recurrence run from the last
-// lane down to k with terminal value 0.
-__device__ __forceinline__ void suffix_scan(double& a, double& b, int lane, int nl) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double a2 = __shfl_down(a, d, 64);
-        const double b2 = __shfl_down(b, d, 64);
-        if (lane + d < nl) {
-            a = a + b * a2;
-            b = b * b2;
-        }
-    }
+// One step of an inclusive scan of affine maps over the 64 lanes: (a, b) of this lane is
+// composed with the (a', b') that the DPP control CTRL moves in (identity (0, 1) where the
+// move has no source or the row is masked off): a <- a + b a', b <- b b'.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v, double identity) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(identity), __double2loint(v), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(identity), __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
-// Prefix scan: x = a + b x_prev, composed with lanes k-1, k-2, ...
-__device__ __forceinline__ void prefix_scan(double& a, double& b, int lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double a2 = __shfl_up(a, d, 64);
-        const double b2 = __shfl_up(b, d, 64);
-        if (lane >= d) {
-            a = a + b * a2;
-            b = b * b2;
-        }
-    }
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void compose_from(double& a, double& b) {
+    const double a2 = dpp_move<CTRL, ROWMASK>(a, 0.0);
+    const double b2 = dpp_move<CTRL, ROWMASK>(b, 1.0);
+    a = a + b * a2;
+    b = b * b2;
+}
+// Inclusive prefix composition over the wavefront: lane k ends with f_k o f_{k-1} o ... o f_0,
+// f_j(z) = a_j + b_j z.  Row shifts by 1, 2, 4, 8 within each 16-lane row, then the last
+// lane of row 0 (2) into row 1 (3), then lane 31 into rows 2 and 3 (DPP row broadcasts):
+// register moves only, no LDS round trips.  Every lane of the wavefront must be active.
+__device__ __forceinline__ void prefix_compose(double& a, double& b) {
+    compose_from<0x111, 0xF>(a, b);  // row_shr:1
+    compose_from<0x112, 0xF>(a, b);  // row_shr:2
+    compose_from<0x114, 0xF>(a, b);  // row_shr:4
+    compose_from<0x118, 0xF>(a, b);  // row_shr:8
+    compose_from<0x142, 0xA>(a, b);  // row_bcast:15 into rows 1 and 3
+    compose_from<0x143, 0xC>(a, b);  // row_bcast:31 into rows 2 and 3
 }
 
 // Hat-block backward solve L0^T z = r for one line, by one full wavefront.
-// r: LDS hat array (nh <= 65), overwritten with z.  Lane k owns hat k; lane 63
-// also owns hat 64 when nh = 65.
+// r: LDS hat array (nh <= 65), overwritten with z.  z_h = (r_h - L0[h+1][h] z_{h+1}) /
+// L0[h][h] runs from the last hat down, so lane k takes hat nl - 1 - k and the suffix
+// becomes a prefix over lanes; hat 64 (nh = 65) is folded into hat 63's map.
 __device__ __forceinline__ void hat_backward(double* r, const HatF& F, int nh, int lane) {
     const int nl = nh < 64 ? nh : 64;
+    const int h = nl - 1 - lane;
     double a = 0.0, b = 1.0;
     double a64 = 0.0;
-    if (lane < nl) {
-        a = r[lane] * F.invd0[lane];
-        b = -F.link0[lane + 1] * F.invd0[lane];
-        if (lane == 63 && nh == 65) {
+    if (h >= 0) {
+        a = r[h] * F.invd0[h];
+        b = -F.link0[h + 1] * F.invd0[h];
+        if (h == 63 && nh == 65) {
             a64 = r[64] * F.invd0[64];
             a = a + b * a64;  // compose with hat 64 (whose own map is constant)
             b = 0.0;
         }
     }
-    suffix_scan(a, b, lane, nl);
-    if (lane < nl) r[lane] = a;
-    if (lane == 63 && nh == 65) r[64] = a64;
+    prefix_compose(a, b);
+    if (h >= 0) r[h] = a;
+    if (h == 63 && nh == 65) r[64] = a64;
 }
 
-// Hat-block forward solve L0 x = z for one line (in place on r).
+// Hat-block forward solve L0 x = z for one line (in place on r): lane k takes hat k.
 __device__ __forceinline__ void hat_forward(double* r, const HatF& F, int nh, int lane) {
     const int nl = nh < 64 ? nh : 64;
     double a = 0.0, b = 0.0;
@@ -86,7 +90,7 @@ __device__ __forceinline__ void hat_forward(double* r, const HatF& F, int nh, in
         a = r[lane] * F.invd0[lane];
         b = -F.link0[lane] * F.invd0[lane];
     }
-    prefix_scan(a, b, lane);
+    prefix_compose(a, b);
     if (lane < nl) r[lane] = a;
     if (nh == 65) {
         const double x63 = __shfl(a, 63, 64);

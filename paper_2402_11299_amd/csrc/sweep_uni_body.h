@@ -2,9 +2,10 @@
 // method and the general kernel).
 //
 // On a mesh of equal elements the factor and operator entries depend only on the
-// degree m, so they are read from one per-degree record table through the scalar
-// cache; with n a multiple of the chains per wavefront every wavefront has one
-// parity, so those reads are wavefront-uniform.  The chain length is a
+// degree m, so they come from one per-degree record table; with n a multiple of the
+// chains per wavefront every wavefront has one parity, so they are wavefront-uniform:
+// the ADI recurrences take them from registers (lane s holds step s, read back with
+// readlane), the other passes through the scalar cache.  The chain length is a
 // compile-time constant CL = p/2; a chain one degree shorter (odd parity, even
 // p) is padded by a phantom degree whose coefficients are zero, which makes it
 // inert in every recurrence, so the unrolled chain loops carry no per-step
@@ -122,6 +123,24 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     const cptr pt = (cptr)(a.ptab);
     auto PT = [&](int m, int k) -> double { return pt[m * 16 + k]; };
 
+    // Lane s of a wavefront holds a coefficient of chain step s (degree pi + 2s) of the
+    // wavefront's parity, and the recurrences read it back with readlane: the unrolled
+    // chains then carry no load latency per step (scalar loads from the table, one step
+    // ahead, stalled every step).
+    auto lane_coef = [&](int k) -> double { return lane < CL ? a.ptab[(pi + 2 * lane) * 16 + k] : 0.0; };
+    auto RL = [&](double v, int s) -> double {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+        return __hiloint2double(hi, lo);
+    };
+    double cb0 = 0.0, cb1 = 0.0, cb2 = 0.0, cf3 = 0.0, cf4 = 0.0;
+    if (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE) {
+        cb0 = lane_coef(0);
+        cb1 = lane_coef(1);
+        cb2 = lane_coef(2);
+        cf3 = lane_coef(3);
+        cf4 = lane_coef(4);
+    }
     auto IDX = [&](const Layout& L, int ln, int pos) -> long { return COL ? addr(L, pos, ln) : addr(L, ln, pos); };
     // byte offset of chain step 0 and byte stride per step (32-bit: loads and stores
     // address a uniform base plus a per-lane 32-bit offset)
@@ -177,16 +196,22 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             double yo_n = 0.0, yp_n = 0.0;
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
-                const int m = pi + 2 * s;
                 const double yo = y[s];
-                double yp = PT(m, 0) * yo;
-                if (s + 1 < CL) yp += PT(m, 1) * yo_n + PT(m, 2) * yp_n;
+                double yp = RL(cb0, s) * yo;
+                if (s + 1 < CL) yp += RL(cb1, s) * yo_n + RL(cb2, s) * yp_n;
                 y[s] = yp;
                 yo_n = yo;
                 yp_n = yp;
             }
             H1[c] = yo_n;
             H2[c] = yp_n;
+        }
+        double cp5 = 0.0, cp6 = 0.0, cp7 = 0.0, cp8 = 0.0;
+        if (MODE == SWEEP_FULL) {
+            cp5 = lane_coef(5);
+            cp6 = lane_coef(6);
+            cp7 = lane_coef(7);
+            cp8 = lane_coef(8);
         }
         __syncthreads();
         for_my_lines([&](int ll) {
@@ -214,9 +239,8 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             double prev = 0.0;
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
-                const int m = pi + 2 * s;
-                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * PT(m, 3);
-                else prev = PT(m, 3) * y[s] + PT(m, 4) * prev;
+                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * RL(cf3, 0);
+                else prev = RL(cf3, s) * y[s] + RL(cf4, s) * prev;
                 y[s] = prev;
             }
             H1[c] = y[0];
@@ -283,9 +307,9 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
                 }
                 const int m = pi + 2 * s;
                 const double x = y[s];
-                double u = PT(m, 5) * x;
-                if (s > 0) u += PT(m, 6) * y[s - 1];
-                if (s + 1 < CL) u += PT(m, 7) * x_n + PT(m, 8) * u_n;
+                double u = RL(cp5, s) * x;
+                if (s > 0) u += RL(cp6, s) * y[s - 1];
+                if (s + 1 < CL) u += RL(cp7, s) * x_n + RL(cp8, s) * u_n;
                 if (s == 0) u += PT(m, 12) * hterm;
                 if (s < CL - 1 || full) *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)((double)gv[s] - u);
                 oo -= so;
