@@ -83,11 +83,12 @@ typedef struct {
                             that axis (else 8); 4 also selects 4-column panels in the internal layout */
     int fixed_rounds;   /* mixed mode: run exactly this many rounds, no host decision (0 = adaptive) */
     int fp32_rounds;    /* mixed mode: leading rounds with FP32 sweeps; later rounds are FP64 (0 = 1) */
-    int col_lines_per_block; /* column half-sweeps only: 1 or 8 lines (0 = as lines_per_block) */
+    int col_lines_per_block; /* column half-sweeps only: 1, 4 or 8 lines (0 = as lines_per_block) */
     double refine_tol;  /* mixed mode: tolerance of the shift family of the FP64 refinement rounds
                            (0 = tol / inner_tol, clamped to [tol, 0.1]); later FP64 rounds
                            take the loosest of 0.1, 0.03, 0.01, ... that the previous round's
                            bound allows (built on first use) */
+    int row_lines_per_block; /* row half-sweeps only: 1, 4 or 8 lines (0 = as lines_per_block) */
 } hpadi_options;
 
 /* ---- 1D operators (Sec. 2, Sec. 3.1, App. A) -------------------------- */

@@ -18,7 +18,7 @@
 #include "host_internal.h"
 
 // The Python binding mirrors these structs with ctypes; their layout is part of the ABI.
-static_assert(sizeof(hpadi_options) == 40 && offsetof(hpadi_options, refine_tol) == 32, "hpadi_options layout");
+static_assert(sizeof(hpadi_options) == 48 && offsetof(hpadi_options, row_lines_per_block) == 40, "hpadi_options layout");
 static_assert(sizeof(hpadi_stats) == 96 && offsetof(hpadi_stats, J_refine) == 68, "hpadi_stats layout");
 
 using hpadi::DimDev;
@@ -1225,15 +1225,22 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     // for, else 4 (measured fastest for FP64 at n = p = 64, equal for FP32); lines per
     // workgroup of the ADI half-sweeps: 1, 4 or 8 per direction
     const int pw = (P->opt.lines_per_block == 8 || P->opt.lines_per_block == 1) ? 8 : 4;
-    auto lines = [&](int req, int n_line_axis) {
+    auto lines = [&](int req, int n_line_axis, int p_line_axis) {
         if (req == 1 && n_line_axis % 64 == 0) return 1;
+        // 8 lines over 4-column panels: a wavefront reads 8 chains x 8 lines, whole 128-byte
+        // lines of FP32 in both directions (2n / 8 wavefronts, within the kernel's limit)
+        if (req == 8 && pw == 4 && n_line_axis % 8 == 0 &&
+            64 * (2 * n_line_axis / 8) <= (p_line_axis / 2 <= 32 ? 1024 : 512))
+            return 8;
         // a wavefront holds 64 / lines chains of one parity: small n needs more lines
         if (n_line_axis % (64 / pw) != 0 && n_line_axis % 4 == 0) return 16;
         return pw;
     };
     // a column pass runs along x (chains of the x basis), a row pass along y
-    P->lpb_col = lines(P->opt.col_lines_per_block > 0 ? P->opt.col_lines_per_block : P->opt.lines_per_block, x->n);
-    P->lpb_row = lines(P->opt.lines_per_block, y->n);
+    P->lpb_col = lines(P->opt.col_lines_per_block > 0 ? P->opt.col_lines_per_block : P->opt.lines_per_block, x->n,
+                       x->p);
+    P->lpb_row = lines(P->opt.row_lines_per_block > 0 ? P->opt.row_lines_per_block : P->opt.lines_per_block, y->n,
+                       y->p);
     L.panel = pw;
     L.nhr = x->nh;
     L.nhc = y->nh;

@@ -123,18 +123,28 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     const cptr pt = (cptr)(a.ptab);
     auto PT = [&](int m, int k) -> double { return pt[m * 16 + k]; };
 
-    // Lane s of a wavefront holds a coefficient of chain step s (degree pi + 2s) of the
-    // wavefront's parity, and the recurrences read it back with readlane: the unrolled
-    // chains then carry no load latency per step (scalar loads from the table, one step
-    // ahead, stalled every step).
-    auto lane_coef = [&](int k) -> double { return lane < CL ? a.ptab[(pi + 2 * lane) * 16 + k] : 0.0; };
-    auto RL = [&](double v, int s) -> double {
-        const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
-        return __hiloint2double(hi, lo);
+    // FP32 storage: lane s of a wavefront holds a coefficient of chain step s (degree
+    // pi + 2s) of the wavefront's parity, and the recurrences read it back with readlane,
+    // so the unrolled chains carry no load latency per step (through the scalar cache the
+    // loads were issued one step ahead and waited on every step).  FP64 storage keeps the
+    // scalar loads: its chain and G~ registers leave no room for the lane copies (they
+    // spilled, and the FP64 half-sweeps ran 13-19% slower).
+    constexpr bool kLaneCoef = sizeof(TIN) == 4;
+    auto lane_coef = [&](int k) -> double {
+        return kLaneCoef && lane < CL ? a.ptab[(pi + 2 * lane) * 16 + k] : 0.0;
+    };
+    auto RL = [&](double v, int s, int k) -> double {
+        if constexpr (!kLaneCoef) {
+            (void)v;
+            return PT(pi + 2 * s, k);
+        } else {
+            const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+            return __hiloint2double(hi, lo);
+        }
     };
     double cb0 = 0.0, cb1 = 0.0, cb2 = 0.0, cf3 = 0.0, cf4 = 0.0;
-    if (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE) {
+    if (kLaneCoef && (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE)) {
         cb0 = lane_coef(0);
         cb1 = lane_coef(1);
         cb2 = lane_coef(2);
@@ -197,8 +207,8 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
                 const double yo = y[s];
-                double yp = RL(cb0, s) * yo;
-                if (s + 1 < CL) yp += RL(cb1, s) * yo_n + RL(cb2, s) * yp_n;
+                double yp = RL(cb0, s, 0) * yo;
+                if (s + 1 < CL) yp += RL(cb1, s, 1) * yo_n + RL(cb2, s, 2) * yp_n;
                 y[s] = yp;
                 yo_n = yo;
                 yp_n = yp;
@@ -207,7 +217,7 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             H2[c] = yp_n;
         }
         double cp5 = 0.0, cp6 = 0.0, cp7 = 0.0, cp8 = 0.0;
-        if (MODE == SWEEP_FULL) {
+        if (kLaneCoef && MODE == SWEEP_FULL) {
             cp5 = lane_coef(5);
             cp6 = lane_coef(6);
             cp7 = lane_coef(7);
@@ -239,8 +249,8 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             double prev = 0.0;
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
-                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * RL(cf3, 0);
-                else prev = RL(cf3, s) * y[s] + RL(cf4, s) * prev;
+                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * RL(cf3, 0, 3);
+                else prev = RL(cf3, s, 3) * y[s] + RL(cf4, s, 4) * prev;
                 y[s] = prev;
             }
             H1[c] = y[0];
@@ -307,9 +317,9 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
                 }
                 const int m = pi + 2 * s;
                 const double x = y[s];
-                double u = RL(cp5, s) * x;
-                if (s > 0) u += RL(cp6, s) * y[s - 1];
-                if (s + 1 < CL) u += RL(cp7, s) * x_n + RL(cp8, s) * u_n;
+                double u = RL(cp5, s, 5) * x;
+                if (s > 0) u += RL(cp6, s, 6) * y[s - 1];
+                if (s + 1 < CL) u += RL(cp7, s, 7) * x_n + RL(cp8, s, 8) * u_n;
                 if (s == 0) u += PT(m, 12) * hterm;
                 if (s < CL - 1 || full) *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)((double)gv[s] - u);
                 oo -= so;

@@ -33,7 +33,8 @@ class hpadi_options(ctypes.Structure):
     _fields_ = [("inner_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
                 ("lines_per_block", ctypes.c_int),
                 ("fixed_rounds", ctypes.c_int), ("fp32_rounds", ctypes.c_int),
-                ("col_lines_per_block", ctypes.c_int), ("refine_tol", ctypes.c_double)]
+                ("col_lines_per_block", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("row_lines_per_block", ctypes.c_int)]
 
 
 class hpadi_krylov_stats(ctypes.Structure):

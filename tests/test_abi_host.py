@@ -146,5 +146,5 @@ def test_struct_layouts_match_the_header(hp):
     """The ctypes mirrors of hpadi_options and hpadi_stats have the layout the library's
     static_asserts fix (size and the offset of the last field added)."""
     import ctypes
-    assert ctypes.sizeof(hp.hpadi_options) == 40 and hp.hpadi_options.refine_tol.offset == 32
+    assert ctypes.sizeof(hp.hpadi_options) == 48 and hp.hpadi_options.row_lines_per_block.offset == 40
     assert ctypes.sizeof(hp.hpadi_stats) == 96 and hp.hpadi_stats.J_refine.offset == 68
