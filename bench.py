@@ -330,6 +330,33 @@ def batch_solve(hp, torch, steps=3, count=512):
             "worst_est_rel_err": worst, "lines_per_block_4": lw.count(4), "lines_per_block_8": lw.count(8)}
 
 
+def schedule_sweep(hp, torch, steps=5):
+    """The mixed solve at n = p = 64 (Dirichlet N = 4095, Neumann N = 4097, the benchmark's
+    right-hand sides) for FP32-round tolerances inner_tol and first-FP64-round tolerances
+    refine_tol (0 = tol / inner_tol), beside the FP64 solve: ms per solve, rounds, ADI
+    iterations and the error bound."""
+    for cfg in (workloads_mod().CFG_MIXED_4K_D, workloads_mod().CFG_MIXED_4K_N):
+        x, y, F = make_problem(hp, torch, cfg)
+        runs = [("fp64", None, None)] + [("mixed", i, r) for i in (3e-7, 1e-6, 3e-6) for r in (0.0, 1e-4, 1e-3)]
+        for prec, inner, rt in runs:
+            o = hp.hpadi_options()
+            if inner is not None:
+                o.inner_tol, o.refine_tol = inner, rt
+            plan = hp.Plan(x, y, cfg.omega2, cfg.tol, prec, options=o)
+            G = plan.load(F)
+            U = torch.empty_like(G)
+            t, st = time_solves(torch, plan, G, U, steps, 1)
+            print(json.dumps({"workload": cfg.name, "precision": prec, "inner_tol": inner, "refine_tol": rt,
+                              "ms": t * 1e3, "rounds": st.rounds, "iters": st.iters, "J": st.J,
+                              "J_refine": st.J_refine, "est_rel_err": st.est_rel_err}), flush=True)
+            plan.close()
+
+
+def workloads_mod():
+    import workloads
+    return workloads
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +366,13 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--only-mixed", action="store_true", help="time only the headline solve (profiling)")
     ap.add_argument("--only-batch", action="store_true", help="run only the 512-instance batch (profiling)")
+    ap.add_argument("--only-varcoef", action="store_true",
+                    help="run only the variable-coefficient ADI-PCG/FCG loops at N = 1023 (profiling)")
+    ap.add_argument("--only-learned", action="store_true",
+                    help="run only the learned-correction training and held-out FCG solves (profiling)")
+    ap.add_argument("--schedules", action="store_true",
+                    help="time the mixed solve at N = 4095 / 4097 for several FP32 and FP64 shift-family "
+                         "tolerances (one JSON line each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -358,6 +392,15 @@ def main():
     torch.cuda.init()
     if args.only_batch:
         print(json.dumps(batch_solve(hp, torch, steps=args.steps)), flush=True)
+        return
+    if args.only_varcoef:
+        print(json.dumps(varcoef_fcg(hp, torch)), flush=True)
+        return
+    if args.only_learned:
+        print(json.dumps(learned_fcg(hp, torch)), flush=True)
+        return
+    if args.schedules:
+        schedule_sweep(hp, torch, steps=max(3, args.steps // 2))
         return
     cfgD = workloads.CFG_MIXED_4K_D
     cfgN = workloads.CFG_MIXED_4K_N

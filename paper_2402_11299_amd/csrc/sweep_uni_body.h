@@ -2,10 +2,13 @@
 // method and the general kernel).
 //
 // On a mesh of equal elements the factor and operator entries depend only on the
-// degree m, so they come from one per-degree record table; with n a multiple of the
-// chains per wavefront every wavefront has one parity, so they are wavefront-uniform:
-// the ADI recurrences take them from registers (lane s holds step s, read back with
-// readlane), the other passes through the scalar cache.  The chain length is a
+// degree m, so they are read from one per-degree record table through the scalar
+// cache; with n a multiple of the chains per wavefront every wavefront has one
+// parity, so those reads are wavefront-uniform.  (Copies of the table held one chain
+// step per lane and read back with readlane ran the FP32 column half-sweep 7% faster,
+// but a lane copy is only valid where the whole wavefront wrote it: lanes of missing
+// lines, masked off by their branch, left stale copies that gave NaN on 8-line
+// workgroups of p = 128.  They are not used.)  The chain length is a
 // compile-time constant CL = p/2; a chain one degree shorter (odd parity, even
 // p) is padded by a phantom degree whose coefficients are zero, which makes it
 // inert in every recurrence, so the unrolled chain loops carry no per-step
@@ -123,34 +126,6 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     const cptr pt = (cptr)(a.ptab);
     auto PT = [&](int m, int k) -> double { return pt[m * 16 + k]; };
 
-    // FP32 storage: lane s of a wavefront holds a coefficient of chain step s (degree
-    // pi + 2s) of the wavefront's parity, and the recurrences read it back with readlane,
-    // so the unrolled chains carry no load latency per step (through the scalar cache the
-    // loads were issued one step ahead and waited on every step).  FP64 storage keeps the
-    // scalar loads: its chain and G~ registers leave no room for the lane copies (they
-    // spilled, and the FP64 half-sweeps ran 13-19% slower).
-    constexpr bool kLaneCoef = sizeof(TIN) == 4;
-    auto lane_coef = [&](int k) -> double {
-        return kLaneCoef && lane < CL ? a.ptab[(pi + 2 * lane) * 16 + k] : 0.0;
-    };
-    auto RL = [&](double v, int s, int k) -> double {
-        if constexpr (!kLaneCoef) {
-            (void)v;
-            return PT(pi + 2 * s, k);
-        } else {
-            const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
-            const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
-            return __hiloint2double(hi, lo);
-        }
-    };
-    double cb0 = 0.0, cb1 = 0.0, cb2 = 0.0, cf3 = 0.0, cf4 = 0.0;
-    if (kLaneCoef && (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE)) {
-        cb0 = lane_coef(0);
-        cb1 = lane_coef(1);
-        cb2 = lane_coef(2);
-        cf3 = lane_coef(3);
-        cf4 = lane_coef(4);
-    }
     auto IDX = [&](const Layout& L, int ln, int pos) -> long { return COL ? addr(L, pos, ln) : addr(L, ln, pos); };
     // byte offset of chain step 0 and byte stride per step (32-bit: loads and stores
     // address a uniform base plus a per-lane 32-bit offset)
@@ -206,22 +181,16 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             double yo_n = 0.0, yp_n = 0.0;
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
+                const int m = pi + 2 * s;
                 const double yo = y[s];
-                double yp = RL(cb0, s, 0) * yo;
-                if (s + 1 < CL) yp += RL(cb1, s, 1) * yo_n + RL(cb2, s, 2) * yp_n;
+                double yp = PT(m, 0) * yo;
+                if (s + 1 < CL) yp += PT(m, 1) * yo_n + PT(m, 2) * yp_n;
                 y[s] = yp;
                 yo_n = yo;
                 yp_n = yp;
             }
             H1[c] = yo_n;
             H2[c] = yp_n;
-        }
-        double cp5 = 0.0, cp6 = 0.0, cp7 = 0.0, cp8 = 0.0;
-        if (kLaneCoef && MODE == SWEEP_FULL) {
-            cp5 = lane_coef(5);
-            cp6 = lane_coef(6);
-            cp7 = lane_coef(7);
-            cp8 = lane_coef(8);
         }
         __syncthreads();
         for_my_lines([&](int ll) {
@@ -249,8 +218,9 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             double prev = 0.0;
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
-                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * RL(cf3, 0, 3);
-                else prev = RL(cf3, s, 3) * y[s] + RL(cf4, s, 4) * prev;
+                const int m = pi + 2 * s;
+                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * PT(m, 3);
+                else prev = PT(m, 3) * y[s] + PT(m, 4) * prev;
                 y[s] = prev;
             }
             H1[c] = y[0];
@@ -317,9 +287,9 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
                 }
                 const int m = pi + 2 * s;
                 const double x = y[s];
-                double u = RL(cp5, s, 5) * x;
-                if (s > 0) u += RL(cp6, s, 6) * y[s - 1];
-                if (s + 1 < CL) u += RL(cp7, s, 7) * x_n + RL(cp8, s, 8) * u_n;
+                double u = PT(m, 5) * x;
+                if (s > 0) u += PT(m, 6) * y[s - 1];
+                if (s + 1 < CL) u += PT(m, 7) * x_n + PT(m, 8) * u_n;
                 if (s == 0) u += PT(m, 12) * hterm;
                 if (s < CL - 1 || full) *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)((double)gv[s] - u);
                 oo -= so;

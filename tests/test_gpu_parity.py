@@ -159,6 +159,28 @@ def test_mixed_error_bound_is_sound(hp, torch, nx, px, bc, w2, draw):
         plan.close()
 
 
+@pytest.mark.parametrize("lw,clw,rlw", [(8, 0, 0), (0, 8, 0), (0, 0, 8), (4, 0, 0)])
+def test_mixed_workgroup_widths_long_chains(hp, torch, lw, clw, rlw):
+    """p = 128 (64-step chains) on few elements, every workgroup width per direction: the
+    last workgroup of a pass holds lines that do not exist, whose lanes must not disturb
+    the others (a regression: lane copies of coefficients left stale by such lanes gave
+    NaN at 8 lines per workgroup)."""
+    nx, px, ny, py, w2, bc = 8, 128, 4, 32, 10.0, "neumann"
+    print(f"widths {lw},{clw},{rlw} at {nx},{px} x {ny},{py}", flush=True)
+    x, y = hp.Op1D(nx, px, 0, 1, bc), hp.Op1D(ny, py, 0, 1, bc)
+    ox, oy = oracle_ops(nx, px, bc), oracle_ops(ny, py, bc)
+    U0 = workloads.decaying_coefficients(nx, px, ny, py, bc, seed=52)
+    G0 = oadi.apply_operator(ox, oy, w2, U0)
+    o = hp.hpadi_options()
+    o.lines_per_block, o.col_lines_per_block, o.row_lines_per_block = lw, clw, rlw
+    plan = hp.Plan(x, y, w2, 1e-10, "mixed", options=o)
+    U, st = plan.solve(torch.from_numpy(G0).cuda())
+    err = oadi.rel_l2_error(U.cpu().numpy(), U0, ox, oy)
+    print(f"  rounds={st.rounds} est={st.est_rel_err:.2e} err={err:.2e}", flush=True)
+    assert st.status == hp.HPADI_OK and err <= 1e-10
+    plan.close()
+
+
 @pytest.mark.parametrize("refine_tol", [0.0, 1e-8])
 def test_mixed_shift_families(hp, torch, refine_tol):
     """A mixed plan builds one shift family for its FP32 round (inner_tol, default 3e-7) and
