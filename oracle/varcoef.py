@@ -21,6 +21,16 @@ basis at the Gauss points, W = w_x w_y^T (weights including the Jacobians):
 With a = 1 this is K (x) M + M (x) K (Sec. 3.2 with omega = 0), which the
 tests check.
 
+Sec. 7's own example adds a potential instead: (-Delta + c) u = f with
+c = -10 log r on (-1, 1)^2, zero Dirichlet, on the tensor mesh graded towards the
+origin with breakpoints -1, -10^-1, ..., -10^-m, 0, 10^-m, ..., 10^-1, 1 per axis,
+solved by CG preconditioned with the ADI inverse of the weak Laplacian
+(K (x) M + M (x) K) at tolerance 1e-4, to a relative residual of 1e-8 (Table 1 of
+the paper lists the iteration counts).  The potential term is integrated with
+the same Gauss rule (a reading: the paper evaluates it through its Chebyshev
+transforms); c has a logarithmic singularity at a mesh vertex, never at a
+Gauss point.
+
 Krylov methods (plain definitions):
 * ``pcg``: preconditioned conjugate gradients (Hestenes-Stiefel form);
 * ``fcg``: flexible CG with truncation m (Notay 2000): each new direction is
@@ -119,25 +129,39 @@ def eval_matrices(B: Basis1D):
 @dataclasses.dataclass
 class VarCoefOperator:
     """The operator U -> Y of the module docstring for one coefficient field
-    a (sampled on the tensor Gauss grid, shape (n_x q_x, n_y q_y))."""
+    a (sampled on the tensor Gauss grid, shape (n_x q_x, n_y q_y)), plus, when c
+    is given (same grid), the potential term of Sec. 7's problem
+    (-Delta + c) u = f:
+
+        sum_e sum_(i,j) w_i w_j c(x_i, y_j) u v  =  E_v^x^T [W . C . (E_v^x U E_v^y^T)] E_v^y."""
 
     bx: Basis1D
     by: Basis1D
     a: np.ndarray
+    c: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.gx, self.gy = gauss_grid(self.bx), gauss_grid(self.by)
         self.Evx, self.Edx = eval_matrices(self.bx)
         self.Evy, self.Edy = eval_matrices(self.by)
         assert self.a.shape == (self.gx.x.size, self.gy.x.size)
-        self.Wa = np.outer(self.gx.w, self.gy.w) * self.a
+        W = np.outer(self.gx.w, self.gy.w)
+        self.Wa = W * self.a
+        self.Wc = None
+        if self.c is not None:
+            assert self.c.shape == self.a.shape
+            self.Wc = W * self.c
 
     def apply(self, U: np.ndarray) -> np.ndarray:
         ux = (self.Evy @ (self.Edx @ U).T).T             # d/dx u at the points: E_d^x U E_v^y^T
         uy = (self.Edy @ (self.Evx @ U).T).T             # d/dy u: E_v^x U E_d^y^T
         Qx = self.Wa * ux
         Qy = self.Wa * uy
-        return np.asarray(self.Edx.T @ (self.Evy.T @ Qx.T).T + self.Evx.T @ (self.Edy.T @ Qy.T).T)
+        Y = np.asarray(self.Edx.T @ (self.Evy.T @ Qx.T).T + self.Evx.T @ (self.Edy.T @ Qy.T).T)
+        if self.Wc is not None:
+            u = (self.Evy @ (self.Evx @ U).T).T          # u at the points: E_v^x U E_v^y^T
+            Y = Y + np.asarray(self.Evx.T @ (self.Evy.T @ (self.Wc * u).T).T)
+        return Y
 
     def dense(self) -> np.ndarray:
         """The N_x N_y square matrix acting on row-major vec(U) (small sizes)."""

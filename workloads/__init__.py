@@ -171,3 +171,27 @@ def singular_coefficient(xs: np.ndarray, ys: np.ndarray, x0: float) -> np.ndarra
 def singular_x0(seed: int) -> float:
     """x0 ~ U(0, 1) for the singular coefficient family."""
     return float(np.random.default_rng(seed).uniform(0.0, 1.0))
+
+
+# ---------------------------------------------------------------------------
+# Sec. 7's singular problem (-Delta - 10 log r) u = 1 on (-1, 1)^2, zero Dirichlet,
+# on a tensor mesh graded towards the origin.
+# ---------------------------------------------------------------------------
+
+def graded_breakpoints(m: int) -> np.ndarray:
+    """-1, -10^-1, ..., -10^-m, 0, 10^-m, ..., 10^-1, 1: 2 (m + 1) cells on (-1, 1)."""
+    pos = 10.0 ** -np.arange(m, 0, -1)          # 10^-m, ..., 10^-1
+    return np.concatenate([[-1.0], -pos[::-1], [0.0], pos, [1.0]])
+
+
+def log_potential(xs: np.ndarray, ys: np.ndarray, scale: float = 10.0) -> np.ndarray:
+    """c(x, y) = -scale log sqrt(x^2 + y^2) on the tensor grid xs x ys."""
+    return -scale * 0.5 * np.log(np.asarray(xs, float)[:, None] ** 2 + np.asarray(ys, float)[None, :] ** 2)
+
+
+def constant_rhs(n: int, p: int, value: float = 1.0) -> np.ndarray:
+    """The piecewise Legendre coefficients of a constant f (degree 0 on every element), as a
+    1D vector of length (p + 1) n in degree-major order; F = outer(fx, fy) in 2D."""
+    f = np.zeros((p + 1) * n)
+    f[:n] = value
+    return f
