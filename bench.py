@@ -293,6 +293,39 @@ def learned_fcg(hp, torch, nfield=9, steps=2000, crop=128):
             "loss_plain_z": L0, "loss_trained": L1, "loss_last50": float(np.mean(hist[-50:])), **res}
 
 
+def section7_table1(hp, torch, steps=3):
+    """Sec. 7's singular problem (-Delta - 10 log r) u = 1 on (-1, 1)^2, zero Dirichlet, graded
+    mesh T_m: CG preconditioned by the FP64 ADI inverse of the weak Laplacian (tolerance
+    1e-4) to a relative residual of 1e-8; iterations (Table 1) and wall time per solve."""
+    import numpy as np
+    import workloads
+    out = {}
+    for m in (1, 2, 3):
+        for p in (8, 16, 32, 64, 128):
+            br = workloads.graded_breakpoints(m)
+            n = br.size - 1
+            x = hp.Op1D(n, p, -1.0, 1.0, "dirichlet", breaks=list(br))
+            xs, _ = hp.VarCoef.grid(x)
+            vc = hp.VarCoef(x, x, None, c=torch.from_numpy(workloads.log_potential(xs, xs)).cuda())
+            pre = hp.Plan(x, x, 0.0, 1e-4, "fp64")
+            f = workloads.constant_rhs(n, p)
+            b = pre.load(torch.from_numpy(np.outer(f, f)).cuda())
+            vc.solve(b, pre, tol=1e-8, maxit=100, truncation=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st, _ = vc.solve(b, pre, tol=1e-8, maxit=100, truncation=0)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / steps
+            out[f"m{m}_p{p}"] = {"N": x.N, "iters": st.iters, "ms": t * 1e3, "true_rel_res": st.true_rel_res,
+                                 "adi_J": pre.J}
+            pre.close()
+            vc.close()
+    log("section 7 (Table 1): " + ", ".join(f"{k} {v['iters']} it {v['ms']:.1f} ms" for k, v in out.items()))
+    return {"workload": "(-Laplace - 10 log r) u = 1 on (-1,1)^2, graded mesh T_m, ADI-PCG (ADI tol 1e-4) to 1e-8",
+            **out}
+
+
 def batch_solve(hp, torch, steps=3, count=512):
     """512 independent screened-Poisson solves (per axis n in {4..64}, p in {8..128}, N <= 2049,
     omega^2 log-uniform in [1e-2, 1e3], random BC) replayed as one graph; G per instance a
@@ -500,6 +533,7 @@ def main():
 
     if not args.only_mixed:
         out["varcoef_fcg"] = varcoef_fcg(hp, torch)
+        out["section7_table1"] = section7_table1(hp, torch)
         out["batch"] = batch_solve(hp, torch)
         out["learned_correction"] = learned_fcg(hp, torch)
 

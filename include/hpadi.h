@@ -243,6 +243,14 @@ int hpadi_varcoef_grid(hpadi_op1d op, double* x, double* w, int len);
  * + (p_x+2)(p_y+2) + (p_y+1)(p_y+2) doubles exceed 160 KiB (p up to about 80). */
 int hpadi_varcoef_create(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int lda, void* hip_stream,
                          hpadi_varcoef* out);
+/* The operator of -div(a grad u) + c u (Sec. 7: the paper's example is
+ * (-Laplace - 10 log r) u = 1, a = 1 and a potential c): a_dev as above or NULL
+ * for a = 1; c_dev the potential on the same Gauss grid (ldc), or NULL for none;
+ * both copied.  Terms on a = 1 and the potential run as separable passes along
+ * each axis (any p); a variable a uses the element kernel (the p limit above).
+ * Host arrays hold the combined quadrature weights of each term. */
+int hpadi_varcoef_create_ex(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int lda, const double* c_dev, int ldc,
+                            void* hip_stream, hpadi_varcoef* out);
 /* Y = A_a U (FP64 device arrays N_x x N_y, row-major), stream-ordered. */
 int hpadi_varcoef_apply(hpadi_varcoef vc, const double* U_dev, int ldu, double* Y_dev, int ldy);
 void hpadi_varcoef_destroy(hpadi_varcoef vc);

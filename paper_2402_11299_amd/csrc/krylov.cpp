@@ -200,11 +200,18 @@ int hpadi_varcoef_grid(hpadi_op1d op, double* x, double* w, int len) {
 
 int hpadi_varcoef_create(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int lda, void* hip_stream,
                          hpadi_varcoef* out) {
-    if (!x || !y || !a_dev || !out) return HPADI_EINVAL;
+    if (!a_dev) return HPADI_EINVAL;
+    return hpadi_varcoef_create_ex(x, y, a_dev, lda, nullptr, 0, hip_stream, out);
+}
+
+int hpadi_varcoef_create_ex(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int lda, const double* c_dev, int ldc,
+                            void* hip_stream, hpadi_varcoef* out) {
+    if (!x || !y || !out) return HPADI_EINVAL;
     *out = nullptr;
     const int qx = x->p + 2, qy = y->p + 2;
-    if (lda < y->n * qy) return HPADI_EINVAL;
-    if (hpadi::vc_lds_bytes(x->p, y->p) > 160 * 1024) return HPADI_EINVAL;
+    const long rows = (long)x->n * qx, cols = (long)y->n * qy;
+    if ((a_dev && lda < cols) || (c_dev && ldc < cols)) return HPADI_EINVAL;
+    if (a_dev && hpadi::vc_lds_bytes(x->p, y->p) > 160 * 1024) return HPADI_EINVAL;
     hpadi_varcoef_s* V = new (std::nothrow) hpadi_varcoef_s();
     if (!V) return HPADI_ENOMEM;
     V->stream = (hipStream_t)hip_stream;
@@ -224,32 +231,90 @@ int hpadi_varcoef_create(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int ld
         delete V;
         return rc;
     }
-    // own copy of the coefficient (compact) and the element scratch
-    const long rows = (long)x->n * qx, cols = (long)y->n * qy;
-    double* a = nullptr;
-    double* ye = nullptr;
-    if (dmalloc(&a, (size_t)rows * cols) != hipSuccess ||
-        dmalloc(&ye, (size_t)x->n * y->n * (x->p + 1) * (y->p + 1)) != hipSuccess) {
-        (void)hipFree(a);
-        delete V;
-        return HPADI_ENOMEM;
-    }
-    V->allocs.push_back(a);
-    V->allocs.push_back(ye);
-    if (hpadi::launch_copy2d(a_dev, lda, a, cols, (int)rows, (int)cols, V->stream) != hipSuccess ||
-        hipStreamSynchronize(V->stream) != hipSuccess) {
-        delete V;
-        return HPADI_EHIP;
-    }
-    d.a = a;
-    d.lda = cols;
-    d.Ye = ye;
     V->opx = *x;
     V->opy = *y;
-    V->a_host.resize((size_t)rows * cols);
-    if (hipMemcpy(V->a_host.data(), a, V->a_host.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
-        delete V;
-        return HPADI_EHIP;
+    V->a_host.assign((size_t)rows * cols, 1.0);
+    // reference weight x Jacobian factor of a term on the Gauss grid
+    auto weights = [&](const std::vector<double>* coef, auto&& factor) {
+        std::vector<double> C((size_t)rows * cols);
+        for (long r = 0; r < rows; ++r)
+            for (long c = 0; c < cols; ++c) {
+                const int ex = (int)(r / qx), i = (int)(r % qx), ey = (int)(c / qy), j = (int)(c % qy);
+                const double f = factor(ax.delta[ex], ay.delta[ey]);
+                C[(size_t)r * cols + c] = (coef ? (*coef)[(size_t)r * cols + c] : 1.0) * ax.w[i] * ay.w[j] * f;
+            }
+        return C;
+    };
+    auto sep_term = [&](const std::vector<double>& C, const double* Ex, const double* Ey) -> int {
+        const double* dC = nullptr;
+        int r2 = upload(V, C, &dC);
+        if (r2 != HPADI_OK) return r2;
+        d.sEx[d.nsep] = Ex;
+        d.sEy[d.nsep] = Ey;
+        d.sC[d.nsep] = dC;
+        d.nsep++;
+        return HPADI_OK;
+    };
+    d.nsep = 0;
+    if (a_dev) {
+        // the gradient terms by the element kernel: own compact copy of a and the element scratch
+        double* a = nullptr;
+        double* ye = nullptr;
+        if (dmalloc(&a, (size_t)rows * cols) != hipSuccess ||
+            dmalloc(&ye, (size_t)x->n * y->n * (x->p + 1) * (y->p + 1)) != hipSuccess) {
+            (void)hipFree(a);
+            delete V;
+            return HPADI_ENOMEM;
+        }
+        V->allocs.push_back(a);
+        V->allocs.push_back(ye);
+        if (hpadi::launch_copy2d(a_dev, lda, a, cols, (int)rows, (int)cols, V->stream) != hipSuccess ||
+            hipStreamSynchronize(V->stream) != hipSuccess) {
+            delete V;
+            return HPADI_EHIP;
+        }
+        d.a = a;
+        d.lda = cols;
+        d.Ye = ye;
+        d.element_terms = 1;
+        if (hipMemcpy(V->a_host.data(), a, V->a_host.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            delete V;
+            return HPADI_EHIP;
+        }
+    } else {
+        // a = 1: the gradient terms as separable passes (d/dx u d/dx v: derivative table on
+        // x, values on y, Jacobian factor delta_y / delta_x; the y pair likewise)
+        d.element_terms = 0;
+        if ((rc = sep_term(weights(nullptr, [](double dx, double dy) { return dy / dx; }), d.Edx, d.Evy)) ||
+            (rc = sep_term(weights(nullptr, [](double dx, double dy) { return dx / dy; }), d.Evx, d.Edy))) {
+            delete V;
+            return rc;
+        }
+    }
+    if (c_dev) {
+        // potential: values on both axes, Jacobian delta_x delta_y / 4
+        std::vector<double> ch((size_t)rows * cols);
+        if (hipMemcpy2D(ch.data(), cols * sizeof(double), c_dev, (size_t)ldc * sizeof(double), cols * sizeof(double),
+                        rows, hipMemcpyDeviceToHost) != hipSuccess) {
+            delete V;
+            return HPADI_EHIP;
+        }
+        if ((rc = sep_term(weights(&ch, [](double dx, double dy) { return dx * dy / 4.0; }), d.Evx, d.Evy))) {
+            delete V;
+            return rc;
+        }
+    }
+    if (d.nsep > 0) {
+        double *t1 = nullptr, *t2 = nullptr;
+        if (dmalloc(&t1, (size_t)rows * y->N) != hipSuccess || dmalloc(&t2, (size_t)rows * cols) != hipSuccess) {
+            (void)hipFree(t1);
+            delete V;
+            return HPADI_ENOMEM;
+        }
+        V->allocs.push_back(t1);
+        V->allocs.push_back(t2);
+        d.T1 = t1;
+        d.T2 = t2;
     }
     *out = V;
     return HPADI_OK;

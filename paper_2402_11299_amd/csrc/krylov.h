@@ -20,6 +20,16 @@ struct VarCoefDev {
     const double* Evy; const double* Edy;
     const double* a; long lda;               // coefficient on the (n_x q_x) x (n_y q_y) grid
     double* Ye;                              // element results [n_x n_y (p_x+1)(p_y+1)]
+    // Separable terms (any degree): Y (+)= sum_t E_t^x^T [C_t . (E_t^x U E_t^y^T)] E_t^y with
+    // E the local value or reference-derivative tables above and C_t the weights of the
+    // term on the Gauss grid (coefficient, Gauss weights and Jacobian factors folded in,
+    // compact (n_x q_x) x (n_y q_y)).  element_terms = 0: the gradient terms are among
+    // them (a = 1); 1: the element kernel computes the gradient terms.
+    int nsep;
+    int element_terms;
+    const double* sEx[3]; const double* sEy[3]; const double* sC[3];
+    double* T1;                              // (n_x q_x) x N_y work
+    double* T2;                              // (n_x q_x) x (n_y q_y) work
 };
 size_t vc_lds_bytes(int px, int py);
 hipError_t launch_vc_apply(const VarCoefDev& v, const double* U, long ldu, double* Y, long ldy, hipStream_t s);

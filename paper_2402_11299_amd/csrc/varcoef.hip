@@ -111,6 +111,83 @@ __global__ void vc_gather_kernel(VarCoefDev v, double* __restrict__ Y, long ldy)
     Y[(long)i * ldy + j] = s;
 }
 
+// ---- separable terms: four passes of banded-block products per term ---------
+// Every pass is a gather along one axis with the local tables: the x-axis maps
+// coefficient rows to Gauss-point rows (and back), the y-axis columns likewise.
+// They hold no per-element dense block, so any degree fits (the element kernel's
+// LDS tile caps p near 80).
+
+// T1[e q + i][j] = sum_l Ex[i][l] U[g_x(e, l)][j]
+__global__ void __launch_bounds__(256) sep_rows_to_points(VarCoefDev v, const double* __restrict__ Ex,
+                                                          const double* __restrict__ U, long ldu) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= v.Ny) return;
+    const int Lx = v.px + 1, e = r / v.qx, i = r - e * v.qx;
+    const int* g = v.l2gx + e * Lx;
+    const double* er = Ex + i * Lx;
+    double s = 0.0;
+    for (int l = 0; l < Lx; ++l) {
+        const int gi = g[l];
+        if (gi >= 0) s += er[l] * U[(long)gi * ldu + j];
+    }
+    v.T1[(long)r * v.Ny + j] = s;
+}
+
+// T2[r][e q + j] = C[r][e q + j] sum_l T1[r][g_y(e, l)] Ey[j][l]
+__global__ void __launch_bounds__(256) sep_cols_to_points(VarCoefDev v, const double* __restrict__ Ey,
+                                                          const double* __restrict__ C) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const int nqy = v.ny * v.qy;
+    if (c >= nqy) return;
+    const int Ly = v.py + 1, e = c / v.qy, jj = c - e * v.qy;
+    const int* g = v.l2gy + e * Ly;
+    const double* t = v.T1 + (long)r * v.Ny;
+    const double* er = Ey + jj * Ly;
+    double s = 0.0;
+    for (int l = 0; l < Ly; ++l) {
+        const int gj = g[l];
+        if (gj >= 0) s += t[gj] * er[l];
+    }
+    v.T2[(long)r * nqy + c] = s * C[(long)r * nqy + c];
+}
+
+// T1[r][j] = sum over the (element, local) owners of column j of sum_jj T2[r][e q + jj] Ey[jj][l]
+__global__ void __launch_bounds__(256) sep_points_to_cols(VarCoefDev v, const double* __restrict__ Ey) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= v.Ny) return;
+    const int Ly = v.py + 1, nqy = v.ny * v.qy;
+    const double* t = v.T2 + (long)r * nqy;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int e = v.owny[4 * j + 2 * b], l = v.owny[4 * j + 2 * b + 1];
+        if (e < 0) continue;
+        for (int jj = 0; jj < v.qy; ++jj) s += t[e * v.qy + jj] * Ey[jj * Ly + l];
+    }
+    v.T1[(long)r * v.Ny + j] = s;
+}
+
+// Y[i][j] (+)= sum over the owners (e, l) of row i of sum_ii Ex[ii][l] T1[e q + ii][j]
+__global__ void __launch_bounds__(256) sep_points_to_rows(VarCoefDev v, const double* __restrict__ Ex, double* Y,
+                                                          long ldy, int accumulate) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= v.Ny) return;
+    const int Lx = v.px + 1;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int e = v.ownx[4 * i + 2 * a], l = v.ownx[4 * i + 2 * a + 1];
+        if (e < 0) continue;
+        for (int ii = 0; ii < v.qx; ++ii) s += Ex[ii * Lx + l] * v.T1[(long)(e * v.qx + ii) * v.Ny + j];
+    }
+    double* y = Y + (long)i * ldy + j;
+    *y = accumulate ? *y + s : s;
+}
+
 // ---- vector kernels (compact row-major N_x x N_y arrays, FP64) ------------
 
 __device__ inline double block_sum(double v, double* red) {
@@ -188,13 +265,25 @@ size_t vc_lds_bytes(int px, int py) {
 }
 
 hipError_t launch_vc_apply(const VarCoefDev& v, const double* U, long ldu, double* Y, long ldy, hipStream_t s) {
-    const size_t lds = vc_lds_bytes(v.px, v.py);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(vc_element_kernel, dim3(v.nx * v.ny), dim3(256), lds, s, v, U, ldu);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(vc_gather_kernel, dim3((v.Ny + 255) / 256, v.Nx), dim3(256), 0, s, v, Y, ldy);
-    return hipGetLastError();
+    hipError_t e = hipSuccess;
+    if (v.element_terms) {
+        const size_t lds = vc_lds_bytes(v.px, v.py);
+        if (lds > 160 * 1024) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(vc_element_kernel, dim3(v.nx * v.ny), dim3(256), lds, s, v, U, ldu);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(vc_gather_kernel, dim3((v.Ny + 255) / 256, v.Nx), dim3(256), 0, s, v, Y, ldy);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const int nqx = v.nx * v.qx, nqy = v.ny * v.qy;
+    for (int t = 0; t < v.nsep; ++t) {
+        hipLaunchKernelGGL(sep_rows_to_points, dim3((v.Ny + 255) / 256, nqx), dim3(256), 0, s, v, v.sEx[t], U, ldu);
+        hipLaunchKernelGGL(sep_cols_to_points, dim3((nqy + 255) / 256, nqx), dim3(256), 0, s, v, v.sEy[t], v.sC[t]);
+        hipLaunchKernelGGL(sep_points_to_cols, dim3((v.Ny + 255) / 256, nqx), dim3(256), 0, s, v, v.sEy[t]);
+        hipLaunchKernelGGL(sep_points_to_rows, dim3((v.Ny + 255) / 256, v.Nx), dim3(256), 0, s, v, v.sEx[t], Y, ldy,
+                           (v.element_terms || t > 0) ? 1 : 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 int dot_parts() { return kDotBlocks; }

@@ -80,6 +80,9 @@ SIGNATURES = {
     "hpadi_varcoef_grid": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, ctypes.c_int]),
     "hpadi_varcoef_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_varcoef_create_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.POINTER(ctypes.c_void_p)]),
     "hpadi_varcoef_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                            ctypes.c_int]),
     "hpadi_varcoef_destroy": (None, [ctypes.c_void_p]),
@@ -283,6 +286,15 @@ def hpadi_varcoef_grid(op, n, p):
     return x, w
 
 
+def hpadi_varcoef_create_ex(x, y, a, c, stream=None):
+    ap, lda = _tptr(a) if a is not None else (None, 0)
+    cp, ldc = _tptr(c) if c is not None else (None, 0)
+    h = ctypes.c_void_p()
+    check(lib().hpadi_varcoef_create_ex(x, y, ap, lda, cp, ldc, _stream_handle(stream), ctypes.byref(h)),
+          "hpadi_varcoef_create_ex")
+    return h
+
+
 def hpadi_varcoef_create(x, y, a, stream=None):
     ap, lda = _tptr(a)
     h = ctypes.c_void_p()
@@ -405,14 +417,19 @@ class Plan:
 
 
 class VarCoef:
-    """Variable-coefficient operator -div(a grad u) on the bases of x and y."""
+    """Operator -div(a grad u) + c u on the bases of x and y (a = None: a = 1; c = None:
+    no potential term)."""
 
-    def __init__(self, x: Op1D, y: Op1D, a, stream=None):
+    def __init__(self, x: Op1D, y: Op1D, a, stream=None, c=None):
         self.x, self.y = x, y
         qx, qy = x.p + 2, y.p + 2
-        if tuple(a.shape) != (x.n * qx, y.n * qy):
-            raise ValueError(f"a must be {x.n * qx} x {y.n * qy} (Gauss grid)")
-        self.handle = hpadi_varcoef_create(x.handle, y.handle, a, stream)
+        for name, f in (("a", a), ("c", c)):
+            if f is not None and tuple(f.shape) != (x.n * qx, y.n * qy):
+                raise ValueError(f"{name} must be {x.n * qx} x {y.n * qy} (Gauss grid)")
+        if c is None and a is not None:
+            self.handle = hpadi_varcoef_create(x.handle, y.handle, a, stream)
+        else:
+            self.handle = hpadi_varcoef_create_ex(x.handle, y.handle, a, c, stream)
 
     @staticmethod
     def grid(op: Op1D):
