@@ -95,3 +95,41 @@ def test_table1_pcg_iterations(hp, m, p):
         assert abs(res.iters - st.iters) <= 1
     pre.close()
     vc.close()
+
+
+@pytest.mark.parametrize("m,p,prec", [(1, 8, "fp64"), (2, 12, "fp64"), (3, 6, "fp64"), (2, 12, "mixed"),
+                                      (3, 16, "mixed")])
+def test_graded_mesh_adi_matches_oracle(hp, m, p, prec):
+    """The screened problem on the graded mesh T_m (omega^2 = 1): FP64 ADI with the oracle's
+    interval and shifts against the oracle's Alg. 2 element by element, and both precisions
+    against the dense Kronecker solve to the tolerance."""
+    import torch
+    print(f"graded ADI m={m} p={p} {prec}", flush=True)
+    B, x = graded(hp, m, p)
+    o = obasis.assemble(B)
+    w2, tol = 1.0, 1e-10
+    F = workloads.legendre_rhs(B.n, p, B.n, p, seed=5)
+    G = oadi.load(o, o, F)
+    if prec == "fp64":
+        oplan = oadi.ADIPlan(o, o, w2, tol)
+        plan = hp.Plan(x, x, w2, tol, "fp64", interval=oplan.interval)
+        assert plan.J == oplan.J
+        U = plan.solve(torch.from_numpy(G).cuda())[0].cpu().numpy()
+        Uo = oplan.solve(G)
+        ediff = np.abs(U - Uo).max() / np.abs(Uo).max()
+        # the GPU runs Alg. 2 in mass-balanced coordinates X = V U L^T and the oracle on U, so
+        # their FP64 roundings differ by up to the mass matrix's condition number times the
+        # unit roundoff (1.6e6 at m = 2, p = 12: elements from 10^-2 to 0.9 wide)
+        cond = np.linalg.cond(o.M.toarray())
+        print(f"  J={plan.J} elementwise max rel diff vs oracle Alg. 2: {ediff:.2e} (cond M {cond:.1e})", flush=True)
+        assert ediff <= max(1e-11, 4 * 2.2e-16 * cond)
+    else:
+        plan = hp.Plan(x, x, w2, tol, "mixed")
+        U, st = plan.solve(torch.from_numpy(G).cuda())
+        U = U.cpu().numpy()
+        print(f"  rounds={st.rounds} est={st.est_rel_err:.2e}", flush=True)
+    Uref = oadi.solve_dense(o, o, w2, G) if B.N <= 50 else oadi.solve_fdm(o, o, w2, G, refine=2)
+    err = oadi.rel_l2_error(U, Uref, o, o)
+    print(f"  error vs exact discrete solution {err:.2e}", flush=True)
+    assert err <= tol * (1 + 1e-3) + 1e-13
+    plan.close()
