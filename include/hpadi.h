@@ -263,7 +263,9 @@ typedef struct {
     double rel_res;       /* ||r_k|| / ||b|| of the recurrence residual at exit */
     double true_rel_res;  /* ||b - A_a x|| / ||b||, recomputed in FP64 at exit */
     double t_ms;          /* host wall time of the call */
-    double reserved[3];
+    int fallback_iters;   /* iterations of plain ADI-PCG after the learned correction was given up */
+    int reserved_i;
+    double reserved[2];
 } hpadi_krylov_stats;
 
 /* ---- Learned correction (an addition to Sec. 7's ADI-preconditioned CG) -- */
@@ -335,7 +337,13 @@ void hpadi_net_destroy(hpadi_net net);
  * solve is the preconditioner (its N_x, N_y must match; typically omega2 = 0,
  * tol 1e-4), or NULL for none.  net: a learned correction applied after each
  * preconditioner application (NULL for none; use truncation >= 1 with it, the
- * corrected preconditioner is not a fixed linear map).  res_hist (host, may be
+ * corrected preconditioner is not a fixed linear map).  Plain ADI-PCG is the
+ * correction's fallback: the corrected run is given up on a non-finite or
+ * non-positive curvature d.A d, on divergence (the residual 100 times its best),
+ * on stagnation (ten iterations without halving the residual) or after maxit / 2
+ * iterations, and PCG with the same preconditioner continues
+ * from the last iterate (from x = 0 if that is not finite or its residual exceeds
+ * ||b||) for the remaining iterations (stats->fallback_iters).  res_hist (host, may be
  * NULL) receives the relative recurrence residual of iterates
  * 0..min(iters, hist_len-1).  Synchronises the stream once per dot product.
  * ENOCONV after maxit iterations (x holds the last iterate); ENOTSPD if

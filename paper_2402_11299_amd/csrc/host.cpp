@@ -1373,10 +1373,11 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
         if (!P->R64 && dmalloc(&P->R64, (size_t)Nx * P->ldw) != hipSuccess) return HPADI_ENOMEM;
         double est = 1.0, last_bound = 0.0;
         const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
-        int k = 0;
+        int k = 0, nfp32 = P->opt.fp32_rounds, k0 = 0;
         bool done = false;
         for (k = 1; k <= maxr; ++k) {
-            const bool fp32 = k <= P->opt.fp32_rounds;
+            // k0: rounds discarded by a restart in FP64 (an FP32 round that overflowed)
+            const bool fp32 = k - k0 <= nfp32;
             const int ts = fp32 ? 4 : 8;
             const ShiftFamily* Fp = fp32 ? &P->first() : &P->refine();
             if (!fp32 && P->opt.fixed_rounds <= 0 && std::isfinite(last_bound) && last_bound > 0.0 &&
@@ -1385,10 +1386,11 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
             const ShiftFamily& F = *Fp;
             const double eps = F.eps;
             // round 1 starts from U = 0 (acc[4], the norm of U before the round, stays 0)
-            if (hpadi::launch_zero_f64(P->acc, k == 1 ? 5 : 1, 1, k == 1 ? 5 : 1, s) != hipSuccess) return HPADI_EHIP;
-            if ((rc = transform_rhs(P, k == 1 ? G : P->R64, k == 1 ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
+            const bool first = k == k0 + 1;
+            if (hpadi::launch_zero_f64(P->acc, first ? 5 : 1, 1, first ? 5 : 1, s) != hipSuccess) return HPADI_EHIP;
+            if ((rc = transform_rhs(P, first ? G : P->R64, first ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
             // the first round writes U, later rounds add their correction to it
-            if ((rc = run_adi(P, F, ts, U, ldu, k > 1, true)) != HPADI_OK) return rc;
+            if ((rc = run_adi(P, F, ts, U, ldu, !first, true)) != HPADI_OK) return rc;
             st.iters += F.J;
             if (fp32) st.fp32_rounds++;
             const bool decide = P->opt.fixed_rounds <= 0 && !fp32;
@@ -1402,7 +1404,17 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
                 }
                 est = fp32 ? 1.0 : lemma_bound(eps, P->acc_host[0], P->acc_host[4]);
                 if (!fp32) last_bound = est;
-                if (std::isnan(P->acc_host[0]) || std::isnan(P->acc_host[4])) break;
+                const bool finite = std::isfinite(P->acc_host[0]) && std::isfinite(P->acc_host[4]);
+                if (!finite && nfp32 > 0 && k < maxr) {
+                    // data beyond the FP32 range (or a non-finite FP32 round): start again
+                    // with FP64 rounds only; a non-finite input fails again and ends ENOCONV
+                    nfp32 = 0;
+                    k0 = k;
+                    last_bound = 0.0;
+                    st.fp32_rounds = 0;
+                    continue;
+                }
+                if (!finite) break;
                 if (decide && est <= P->tol) {
                     done = true;
                     break;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -16,6 +17,9 @@
 #include "krylov_internal.h"
 
 using hpadi_host::dmalloc;
+
+static_assert(sizeof(hpadi_krylov_stats) == 64 && offsetof(hpadi_krylov_stats, fallback_iters) == 40,
+              "hpadi_krylov_stats layout");
 
 namespace {
 
@@ -377,77 +381,128 @@ int fcg_core(hpadi_varcoef_s* V, hpadi_plan precond, hpadi_net net, const double
         st.precond_calls++;
         return HPADI_OK;
     };
-    const int m = truncation;
+    const int ring = std::max(truncation, 1);
+    std::vector<double> dq_hist(ring + 1, 0.0);
     int k = 0;
     bool converged = bn == 0.0;
     double rel = converged ? 0.0 : 1.0;
-    double rz_old = 0.0;
-    std::vector<double> dq_hist(std::max(m, 1) + 1, 0.0);
-    const int ring = std::max(m, 1);
-    while (!converged && k < maxit) {
-        if ((rc = precondition()) != HPADI_OK) return rc;
-        if (net) {
-            bool applied = false;
-            if ((rc = net_correct(net, V, V->r, V->z, k, &applied)) != HPADI_OK) return rc;
-            if (applied) st.corrections++;
-        }
-        if (observe && (rc = observe(k, V->r, V->z, xc)) != HPADI_OK) return rc;
-        double* dk = V->d[k % ring];
-        double* qk = V->q[k % ring];
-        if (m == 0) {
-            // PCG: d = z + beta d, beta = (r.z) / (r_old.z_old)
-            double rz;
-            if ((rc = dots(V, V->r, {V->z}, &rz)) != HPADI_OK) return rc;
-            const double beta = k == 0 ? 0.0 : rz / rz_old;
-            rz_old = rz;
-            if (hpadi::launch_xpby(dk, V->z, beta, n, s) != hipSuccess) return HPADI_EHIP;
-        } else {
-            // FCG(m): d = z - sum_{i in window} (z.q_i / d_i.q_i) d_i
-            const int nw = std::min(k, m);
-            double c[4] = {0, 0, 0, 0};
-            if (nw > 0) {
-                hpadi::MultiB mb{};
-                mb.nb = nw;
-                for (int i = 0; i < nw; ++i) mb.b[i] = V->q[(k - 1 - i) % ring];
-                if (hpadi::launch_multidot(V->z, mb, n, V->part, V->dots, s) != hipSuccess ||
-                    hipMemcpyAsync(V->dots_host, V->dots, nw * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                    hipStreamSynchronize(s) != hipSuccess)
-                    return HPADI_EHIP;
-                for (int i = 0; i < nw; ++i) c[i] = -V->dots_host[i] / dq_hist[(k - 1 - i) % ring];
+    // Iterations k0 .. kmax - 1 from the current x and r with truncation m (0 = PCG) and
+    // the network nn (or none).  A corrected run gives up (returns with *give_up) on a
+    // non-finite or non-positive curvature, on divergence (the residual 100 times its
+    // best) and after kmax iterations; a plain run ends ENOTSPD on a non-positive one.
+    auto iterate = [&](int m, hpadi_net nn, int kmax, bool* give_up) -> int {
+        *give_up = false;
+        double rz_old = 0.0, best = rel, mark = rel;
+        const int k0 = k;
+        int k_mark = k;  // iteration of the last halving of the residual
+        while (!converged && k < kmax) {
+            int r2;
+            if ((r2 = precondition()) != HPADI_OK) return r2;
+            if (nn) {
+                bool applied = false;
+                if ((r2 = net_correct(nn, V, V->r, V->z, k, &applied)) != HPADI_OK) return r2;
+                if (applied) st.corrections++;
             }
-            // the oldest direction of the ring is overwritten by d_k: form d_k in z first
-            if (nw > 0) {
-                hpadi::MultiB xs{};
-                hpadi::Coefs cc{};
-                xs.nb = nw;
-                for (int i = 0; i < nw; ++i) {
-                    xs.b[i] = V->d[(k - 1 - i) % ring];
-                    cc.c[i] = c[i];
+            if (observe && (r2 = observe(k, V->r, V->z, xc)) != HPADI_OK) return r2;
+            const int kk = k - k0;  // directions of this run only
+            double* dk = V->d[kk % ring];
+            double* qk = V->q[kk % ring];
+            if (m == 0) {
+                // PCG: d = z + beta d, beta = (r.z) / (r_old.z_old)
+                double rz;
+                if ((r2 = dots(V, V->r, {V->z}, &rz)) != HPADI_OK) return r2;
+                const double beta = kk == 0 ? 0.0 : rz / rz_old;
+                rz_old = rz;
+                if (hpadi::launch_xpby(dk, V->z, beta, n, s) != hipSuccess) return HPADI_EHIP;
+            } else {
+                // FCG(m): d = z - sum_{i in window} (z.q_i / d_i.q_i) d_i
+                const int nw = std::min(kk, m);
+                double c[4] = {0, 0, 0, 0};
+                if (nw > 0) {
+                    hpadi::MultiB mb{};
+                    mb.nb = nw;
+                    for (int i2 = 0; i2 < nw; ++i2) mb.b[i2] = V->q[(kk - 1 - i2) % ring];
+                    if (hpadi::launch_multidot(V->z, mb, n, V->part, V->dots, s) != hipSuccess ||
+                        hipMemcpyAsync(V->dots_host, V->dots, nw * sizeof(double), hipMemcpyDeviceToHost, s) !=
+                            hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess)
+                        return HPADI_EHIP;
+                    for (int i2 = 0; i2 < nw; ++i2) c[i2] = -V->dots_host[i2] / dq_hist[(kk - 1 - i2) % ring];
                 }
-                if (hpadi::launch_axpys(V->z, xs, cc, n, s) != hipSuccess) return HPADI_EHIP;
+                // the oldest direction of the ring is overwritten by d_k: form d_k in z first
+                if (nw > 0) {
+                    hpadi::MultiB xs{};
+                    hpadi::Coefs cc{};
+                    xs.nb = nw;
+                    for (int i2 = 0; i2 < nw; ++i2) {
+                        xs.b[i2] = V->d[(kk - 1 - i2) % ring];
+                        cc.c[i2] = c[i2];
+                    }
+                    if (hpadi::launch_axpys(V->z, xs, cc, n, s) != hipSuccess) return HPADI_EHIP;
+                }
+                if (hipMemcpyAsync(dk, V->z, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    return HPADI_EHIP;
             }
-            if (hipMemcpyAsync(dk, V->z, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return HPADI_EHIP;
+            // q = A d; alpha = d.r / d.q
+            if (hpadi::launch_vc_apply(V->dev, dk, Ny, qk, Ny, s) != hipSuccess) return HPADI_EHIP;
+            double dd[2];
+            if ((r2 = dots(V, dk, {qk, V->r}, dd)) != HPADI_OK) return r2;
+            const double dq = dd[0];
+            if (!(dq > 0.0) || !std::isfinite(dq)) {
+                if (nn) {
+                    *give_up = true;
+                    return HPADI_OK;
+                }
+                return HPADI_ENOTSPD;
+            }
+            dq_hist[kk % ring] = dq;
+            const double alpha = (m == 0 ? rz_old : dd[1]) / dq;
+            if ((r2 = axpy(V, xc, alpha, dk)) != HPADI_OK || (r2 = axpy(V, V->r, -alpha, qk)) != HPADI_OK) return r2;
+            ++k;
+            double rr;
+            if ((r2 = dots(V, V->r, {V->r}, &rr)) != HPADI_OK) return r2;
+            rel = std::sqrt(std::max(rr, 0.0)) / bn;
+            if (res_hist && k < hist_len) res_hist[k] = rel;
+            if (!std::isfinite(rel) || (nn && rel > 100.0 * best)) {
+                if (nn) *give_up = true;
+                return HPADI_OK;
+            }
+            best = std::min(best, rel);
+            if (rel <= 0.5 * mark) {
+                mark = rel;
+                k_mark = k;
+            } else if (nn && k - k_mark >= 10) {
+                // stagnation: ten iterations without halving the residual
+                *give_up = true;
+                return HPADI_OK;
+            }
+            if (rel <= tol) converged = true;
         }
-        // q = A d; alpha = d.r / d.q
-        if (hpadi::launch_vc_apply(V->dev, dk, Ny, qk, Ny, s) != hipSuccess) return HPADI_EHIP;
-        double dd[2];
-        if ((rc = dots(V, dk, {qk, V->r}, dd)) != HPADI_OK) return rc;
-        const double dq = dd[0];
-        if (!(dq > 0.0) || !std::isfinite(dq)) {
-            rc = HPADI_ENOTSPD;
-            break;
-        }
-        dq_hist[k % ring] = dq;
-        const double alpha = (m == 0 ? rz_old : dd[1]) / dq;
-        if ((rc = axpy(V, xc, alpha, dk)) != HPADI_OK || (rc = axpy(V, V->r, -alpha, qk)) != HPADI_OK) return rc;
-        ++k;
+        if (nn && !converged) *give_up = true;
+        return HPADI_OK;
+    };
+    bool give_up = false;
+    // with a network: at most half the iterations, then plain ADI-PCG from the last finite
+    // iterate (from x = 0 if none) for the rest
+    rc = iterate(truncation, net, net ? std::max(1, maxit / 2) : maxit, &give_up);
+    if (rc == HPADI_OK && net && give_up && !converged) {
+        // r = b - A x; restart from 0 when x or that residual is not finite
+        if (hpadi::launch_vc_apply(V->dev, xc, Ny, V->z, Ny, s) != hipSuccess) return HPADI_EHIP;
+        if (hipMemcpyAsync(V->r, bc, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            axpy(V, V->r, -1.0, V->z) != HPADI_OK)
+            return HPADI_EHIP;
         double rr;
         if ((rc = dots(V, V->r, {V->r}, &rr)) != HPADI_OK) return rc;
         rel = std::sqrt(std::max(rr, 0.0)) / bn;
-        if (res_hist && k < hist_len) res_hist[k] = rel;
-        if (!std::isfinite(rel)) break;
-        if (rel <= tol) converged = true;
+        if (!std::isfinite(rel) || rel > 1.0) {
+            if (hipMemsetAsync(xc, 0, n * sizeof(double), s) != hipSuccess ||
+                hipMemcpyAsync(V->r, bc, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return HPADI_EHIP;
+            rel = 1.0;
+        }
+        const int k_switch = k;
+        rc = iterate(0, nullptr, maxit, &give_up);
+        st.fallback_iters = k - k_switch;
     }
     if (rc != HPADI_OK && rc != HPADI_ENOTSPD) return rc;
     // true residual b - A x, and x to the caller's layout

@@ -40,7 +40,8 @@ class hpadi_options(ctypes.Structure):
 class hpadi_krylov_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("precond_calls", ctypes.c_int),
                 ("corrections", ctypes.c_int), ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
-                ("t_ms", ctypes.c_double), ("reserved", ctypes.c_double * 3)]
+                ("t_ms", ctypes.c_double), ("fallback_iters", ctypes.c_int), ("reserved_i", ctypes.c_int),
+                ("reserved", ctypes.c_double * 2)]
 
 
 # name -> (restype, argtypes), in the order of include/hpadi.h

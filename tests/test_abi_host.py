@@ -148,3 +148,4 @@ def test_struct_layouts_match_the_header(hp):
     import ctypes
     assert ctypes.sizeof(hp.hpadi_options) == 48 and hp.hpadi_options.row_lines_per_block.offset == 40
     assert ctypes.sizeof(hp.hpadi_stats) == 96 and hp.hpadi_stats.J_refine.offset == 68
+    assert ctypes.sizeof(hp.hpadi_krylov_stats) == 64 and hp.hpadi_krylov_stats.fallback_iters.offset == 40

@@ -145,7 +145,8 @@ def _varcoef_problem(hp, cfg, seed):
 def test_learned_fcg_small(hp):
     """Pairs from plain ADI-PCG iterates on a small problem, a short training, and the
     corrected FCG: it must still reach the tolerance on the FP64 true residual (the
-    correction is checked for descent and dropped otherwise)."""
+    energy-optimal combination never does worse than the plain preconditioned residual
+    in the energy norm; a corrected run that fails falls back to plain ADI-PCG)."""
     import torch
     cfg = workloads.Problem("varcoef_n8_p8", 8, 8, 8, 8, 0.0, "dirichlet", 1e-10, 11)
     x, y, vc, a = _varcoef_problem(hp, cfg, seed=11)
