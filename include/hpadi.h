@@ -352,6 +352,55 @@ int hpadi_fcg_solve(hpadi_varcoef vc, hpadi_plan precond, hpadi_net net, const d
                     int ldx, double tol, int maxit, int truncation, double* res_hist, int hist_len,
                     hpadi_krylov_stats* stats);
 
+/* ---- Grid transforms and the Burgers time-stepper (Sec. 6) ------------- */
+
+/* The grid of one axis (host): on every element the m = p + 1 Chebyshev points of the
+ * first kind t_k = sin(pi (m - 2k - 1) / (2m)), k = 0..m-1 (descending; Sec. 6 counts
+ * them from 1), mapped to the element: x[e m + k] = x_e + (1 + t_k) delta_e / 2.
+ * len >= n m.  Values on a 2D grid are stored element-major along each axis: entry
+ * (e_x m_x + k, e_y m_y + j), an (n_x m_x) x (n_y m_y) array (n m = Nleg). */
+int hpadi_grid(hpadi_op1d op, double* x, int len);
+
+/* Host copy of one reference-element table of degree p, row-major (p+1) x (p+1), for
+ * tests: which = 0 the transform F_p (Legendre coefficient k from value i), 1 its inverse
+ * (P_k(t_i)), 2 the local basis at the points (columns: left hat, right hat, W_0..W_{p-2}),
+ * 3 their t-derivatives.  Host-only. */
+int hpadi_transform_export(int p, int which, double* buf, int len);
+
+typedef struct hpadi_transform_s* hpadi_transform;
+/* Reference-element tables of both axes on the device, and an intermediate array of
+ * max(Nleg_x, N_x) x Nleg_y doubles.  hip_stream: the stream of every call on the handle.
+ * The operators are copied. */
+int hpadi_transform_create(hpadi_op1d x, hpadi_op1d y, void* hip_stream, hpadi_transform* out);
+/* F = F_x V F_y^T (Sec. 6, the transform F_p on every element along each axis): the
+ * piecewise Legendre coefficients (Nleg_x x Nleg_y, degree-major) of the interpolant of
+ * the grid values V (element-major).  FP64 device arrays; V and F must not overlap. */
+int hpadi_values_to_legendre(hpadi_transform t, const double* V_dev, int ldv, double* F_dev, int ldf);
+/* V = F_x^{-1} F F_y^{-T}: the piecewise Legendre series F evaluated on the grid. */
+int hpadi_legendre_to_values(hpadi_transform t, const double* F_dev, int ldf, double* V_dev, int ldv);
+/* Grid values of u = Q_x U Q_y^T (deriv_x = 0), i.e. F_x^{-1} R_x U R_y^T F_y^{-T}, or of
+ * du/dx (deriv_x = 1), F_x^{-1} D_x U R_y^T F_y^{-T} (Sec. 6).  U_dev: N_x x N_y
+ * coefficients in the hat+bubble basis; V_dev: (n_x m_x) x (n_y m_y). */
+int hpadi_q_to_values(hpadi_transform t, int deriv_x, const double* U_dev, int ldu, double* V_dev, int ldv);
+void hpadi_transform_destroy(hpadi_transform t);
+
+/* u_t + u u_x = eps Laplace(u) on the rectangle of the operators, with their (zero)
+ * boundary conditions, by the splitting of Sec. 6: implicit Euler for the viscous part,
+ * (I - dt eps Laplace) u_{k+1/2} = u_k, solved by the ADI plan of the screened problem with
+ * omega^2 = 1 / (dt eps) and right-hand side omega^2 u_k; then explicit Euler for the
+ * convection at the grid points, u_{k+1} = u_{k+1/2} - dt u_{k+1/2} d/dx u_{k+1/2} (the
+ * sign of the equation as written), and back to Legendre coefficients by F_p.  tol,
+ * precision, opts: those of the plan (hpadi_plan_create_ex).  EINVAL unless eps > 0 and
+ * dt > 0. */
+typedef struct hpadi_burgers_s* hpadi_burgers;
+int hpadi_burgers_create(hpadi_op1d x, hpadi_op1d y, double eps, double dt, double tol, int precision,
+                         const hpadi_options* opts, void* hip_stream, hpadi_burgers* out);
+/* Advance F_dev (Nleg_x x Nleg_y piecewise Legendre coefficients of u, FP64 device, in place)
+ * by nsteps steps.  stats: the last step's solve (may be NULL).  ENOCONV when a solve
+ * missed its tolerance: F then holds the step that used it, and no further step is taken. */
+int hpadi_burgers_step(hpadi_burgers b, double* F_dev, int ldf, int nsteps, hpadi_stats* stats);
+void hpadi_burgers_destroy(hpadi_burgers b);
+
 /* ---- Measurement ------------------------------------------------------- */
 
 /* Kernel timing for roofline measurement: while enabled, HIP events are

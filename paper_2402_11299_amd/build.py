@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhpadi.so")
 
-SOURCES = ["host.cpp", "krylov.cpp", "net.cpp", "kernels.hip", "sweep.hip", "sweep_uni.hip", "sweep_group.hip", "varcoef.hip", "net.hip"]
+SOURCES = ["host.cpp", "krylov.cpp", "net.cpp", "kernels.hip", "sweep.hip", "sweep_uni.hip", "sweep_group.hip", "varcoef.hip", "net.hip", "transforms.cpp", "transforms.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -161,12 +161,13 @@ struct Residual {
 };
 hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s);
 
-// G = T_x F T_y^T, two elementwise gather passes (Sec. 3.2).
+// G = scale T_x F T_y^T, two elementwise gather passes (Sec. 3.2).
 hipError_t launch_load(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H,
-                       long ldh, double* G, long ldg, hipStream_t s);
+                       long ldh, double* G, long ldg, hipStream_t s, double scale = 1.0);
 // The same for the columns j0 <= j < j0 + ncols of G only; H then holds ncols columns.
 hipError_t launch_load_cols(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H,
-                            long ldh, double* G, long ldg, int j0, int ncols, hipStream_t s);
+                            long ldh, double* G, long ldg, int j0, int ncols, hipStream_t s,
+                            double scale = 1.0);
 
 // Fixed device scratch of the allocation-free load (16 MiB per device, kept until the
 // process ends), and the device address of the current device's copy.

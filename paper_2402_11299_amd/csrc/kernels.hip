@@ -315,13 +315,13 @@ __global__ void __launch_bounds__(256) load_rows(DimDev dy, const double* F, lon
     H[(long)i * ldh + jj] = gather_load(dy, F + (long)i * ldf, 1, j0 + jj);
 }
 
-// G[i][j0 + jj] = (T_x H[:, jj])[i], jj < ncols.
+// G[i][j0 + jj] = scale (T_x H[:, jj])[i], jj < ncols.
 __global__ void __launch_bounds__(256) load_cols(DimDev dx, const double* H, long ldh, double* G, long ldg,
-                                                 int j0, int ncols) {
+                                                 int j0, int ncols, double scale) {
     const int jj = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (jj >= ncols || i >= dx.N) return;
-    G[(long)i * ldg + j0 + jj] = gather_load(dx, H + jj, ldh, i);
+    G[(long)i * ldg + j0 + jj] = scale * gather_load(dx, H + jj, ldh, i);
 }
 
 __global__ void __launch_bounds__(256) convert_kernel(const double* src, long lds, float* dst, long ldd,
@@ -377,17 +377,17 @@ hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s) {
 }
 
 hipError_t launch_load(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H, long ldh, double* G,
-                       long ldg, hipStream_t s) {
-    return launch_load_cols(dx, dy, F, ldf, H, ldh, G, ldg, 0, dy.N, s);
+                       long ldg, hipStream_t s, double scale) {
+    return launch_load_cols(dx, dy, F, ldf, H, ldh, G, ldg, 0, dy.N, s, scale);
 }
 
 hipError_t launch_load_cols(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H, long ldh,
-                            double* G, long ldg, int j0, int ncols, hipStream_t s) {
+                            double* G, long ldg, int j0, int ncols, hipStream_t s, double scale) {
     if (ncols <= 0) return hipSuccess;
     hipLaunchKernelGGL(load_rows, grid2(ncols, dx.Nleg), dim3(256), 0, s, dy, F, ldf, H, ldh, dx.Nleg, j0, ncols);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(load_cols, grid2(ncols, dx.N), dim3(256), 0, s, dx, H, ldh, G, ldg, j0, ncols);
+    hipLaunchKernelGGL(load_cols, grid2(ncols, dx.N), dim3(256), 0, s, dx, H, ldh, G, ldg, j0, ncols, scale);
     return hipGetLastError();
 }
 

@@ -110,6 +110,23 @@ SIGNATURES = {
     "hpadi_fcg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, _c_double_p, ctypes.c_int, ctypes.POINTER(hpadi_krylov_stats)]),
+    "hpadi_grid": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, ctypes.c_int]),
+    "hpadi_transform_export": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_double_p, ctypes.c_int]),
+    "hpadi_transform_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_values_to_legendre": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                ctypes.c_int]),
+    "hpadi_legendre_to_values": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                ctypes.c_int]),
+    "hpadi_q_to_values": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_int]),
+    "hpadi_transform_destroy": (None, [ctypes.c_void_p]),
+    "hpadi_burgers_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_burgers_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p]),
+    "hpadi_burgers_destroy": (None, [ctypes.c_void_p]),
     "hpadi_plan_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "hpadi_plan_timing_read": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, _c_int_p]),
     "hpadi_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -325,6 +342,69 @@ def hpadi_fcg_solve(vc, precond, b, x, tol, maxit, truncation, hist_len=0, raise
     if rc != HPADI_OK and (raise_on_noconv or rc != HPADI_ENOCONV):
         raise HpadiError(rc, "hpadi_fcg_solve")
     return st, hist[:min(st.iters + 1, hist_len)] if hist_len > 0 else None
+
+
+def hpadi_grid(op, n, p):
+    import numpy as np
+    x = np.zeros(n * (p + 1))
+    check(lib().hpadi_grid(op, _dptr(x), x.size), "hpadi_grid")
+    return x
+
+
+def hpadi_transform_export(p, which):
+    import numpy as np
+    buf = np.zeros((p + 1) * (p + 1))
+    check(lib().hpadi_transform_export(int(p), int(which), _dptr(buf), buf.size), "hpadi_transform_export")
+    return buf.reshape(p + 1, p + 1)
+
+
+def hpadi_transform_create(x, y, stream=None):
+    h = ctypes.c_void_p()
+    check(lib().hpadi_transform_create(x, y, _stream_handle(stream), ctypes.byref(h)), "hpadi_transform_create")
+    return h
+
+
+def hpadi_values_to_legendre(t, V, F):
+    vp, ldv = _tptr(V)
+    fp, ldf = _tptr(F)
+    check(lib().hpadi_values_to_legendre(t, vp, ldv, fp, ldf), "hpadi_values_to_legendre")
+
+
+def hpadi_legendre_to_values(t, F, V):
+    fp, ldf = _tptr(F)
+    vp, ldv = _tptr(V)
+    check(lib().hpadi_legendre_to_values(t, fp, ldf, vp, ldv), "hpadi_legendre_to_values")
+
+
+def hpadi_q_to_values(t, deriv_x, U, V):
+    up, ldu = _tptr(U)
+    vp, ldv = _tptr(V)
+    check(lib().hpadi_q_to_values(t, int(deriv_x), up, ldu, vp, ldv), "hpadi_q_to_values")
+
+
+def hpadi_transform_destroy(t):
+    lib().hpadi_transform_destroy(t)
+
+
+def hpadi_burgers_create(x, y, eps, dt, tol, precision=HPADI_FP64, options=None, stream=None):
+    h = ctypes.c_void_p()
+    check(lib().hpadi_burgers_create(x, y, float(eps), float(dt), float(tol), int(precision),
+                                     ctypes.byref(options) if options is not None else None,
+                                     _stream_handle(stream), ctypes.byref(h)), "hpadi_burgers_create")
+    return h
+
+
+def hpadi_burgers_step(b, F, nsteps, raise_on_noconv=True):
+    fp, ldf = _tptr(F)
+    st = hpadi_stats()
+    rc = lib().hpadi_burgers_step(b, fp, ldf, int(nsteps), ctypes.byref(st))
+    if rc != HPADI_OK and (raise_on_noconv or rc != HPADI_ENOCONV):
+        raise HpadiError(rc, "hpadi_burgers_step")
+    return st
+
+
+def hpadi_burgers_destroy(b):
+    lib().hpadi_burgers_destroy(b)
 
 
 def hpadi_plan_timing(plan, enable):
@@ -617,6 +697,82 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None) is not None:
             lib().hpadi_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Transform:
+    """Grid transforms of Sec. 6 on the GPU: grid values <-> piecewise Legendre
+    coefficients, and hat+bubble coefficients -> grid values of u or du/dx."""
+
+    def __init__(self, x: Op1D, y: Op1D, stream=None):
+        self.x, self.y = x, y
+        self.handle = hpadi_transform_create(x.handle, y.handle, stream)
+
+    @staticmethod
+    def grid(op: Op1D):
+        return hpadi_grid(op.handle, op.n, op.p)
+
+    def _out(self, rows, cols, like):
+        import torch
+        return torch.empty((rows, cols), dtype=torch.float64, device=like.device)
+
+    def values_to_legendre(self, V):
+        if tuple(V.shape) != (self.x.Nleg, self.y.Nleg):
+            raise ValueError(f"V must be {self.x.Nleg} x {self.y.Nleg}")
+        F = self._out(self.x.Nleg, self.y.Nleg, V)
+        hpadi_values_to_legendre(self.handle, V, F)
+        return F
+
+    def legendre_to_values(self, F):
+        if tuple(F.shape) != (self.x.Nleg, self.y.Nleg):
+            raise ValueError(f"F must be {self.x.Nleg} x {self.y.Nleg}")
+        V = self._out(self.x.Nleg, self.y.Nleg, F)
+        hpadi_legendre_to_values(self.handle, F, V)
+        return V
+
+    def q_to_values(self, U, deriv_x=False):
+        if tuple(U.shape) != (self.x.N, self.y.N):
+            raise ValueError(f"U must be {self.x.N} x {self.y.N}")
+        V = self._out(self.x.Nleg, self.y.Nleg, U)
+        hpadi_q_to_values(self.handle, deriv_x, U, V)
+        return V
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            hpadi_transform_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Burgers:
+    """The IMEX time-stepper of Sec. 6 for u_t + u u_x = eps Laplace(u)."""
+
+    def __init__(self, x: Op1D, y: Op1D, eps, dt, tol=1e-12, precision="fp64", options=None, stream=None):
+        self.x, self.y = x, y
+        self.eps, self.dt = eps, dt
+        code = HPADI_FP64 if precision == "fp64" else HPADI_MIXED
+        self.handle = hpadi_burgers_create(x.handle, y.handle, eps, dt, tol, code, options, stream)
+
+    def step(self, F, nsteps=1, raise_on_noconv=True):
+        """Advance F (Nleg_x x Nleg_y Legendre coefficients, CUDA float64) in place."""
+        if tuple(F.shape) != (self.x.Nleg, self.y.Nleg):
+            raise ValueError(f"F must be {self.x.Nleg} x {self.y.Nleg}")
+        return hpadi_burgers_step(self.handle, F, nsteps, raise_on_noconv)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            hpadi_burgers_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

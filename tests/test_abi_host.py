@@ -149,3 +149,47 @@ def test_struct_layouts_match_the_header(hp):
     assert ctypes.sizeof(hp.hpadi_options) == 48 and hp.hpadi_options.row_lines_per_block.offset == 40
     assert ctypes.sizeof(hp.hpadi_stats) == 96 and hp.hpadi_stats.J_refine.offset == 68
     assert ctypes.sizeof(hp.hpadi_krylov_stats) == 64 and hp.hpadi_krylov_stats.fallback_iters.offset == 40
+
+
+@pytest.mark.parametrize("n,p,breaks", [(1, 2, None), (3, 4, [0.0, 0.1, 0.5, 2.0]), (4, 64, None)])
+def test_host_grid_matches_oracle(hp, n, p, breaks):
+    """The Chebyshev grid of Sec. 6 (host): the library's points against the oracle's."""
+    from oracle import transforms as otr
+    a, b = (breaks[0], breaks[-1]) if breaks else (-1.0, 3.0)
+    op = hp.Op1D(n, p, a, b, "dirichlet", breaks)
+    x = hp.Transform.grid(op)
+    ref = otr.grid(obasis.make_basis(n, p, a, b, "dirichlet", breaks))
+    assert np.abs(x - ref).max() <= 4e-16 * max(abs(a), abs(b))
+
+
+def test_host_burgers_rejects_bad_parameters(hp):
+    op = hp.Op1D(2, 4)
+    h = hp.ctypes.c_void_p()
+    for eps, dt in ((0.0, 1e-3), (0.1, 0.0), (-0.1, 1e-3), (float("nan"), 1e-3), (0.1, float("inf"))):
+        rc = hp.lib().hpadi_burgers_create(op.handle, op.handle, eps, dt, 1e-10, 0, None, None, hp.ctypes.byref(h))
+        assert rc == hp.HPADI_EINVAL and not h.value
+
+
+@pytest.mark.parametrize("p", [1, 2, 7, 16, 64, 128])
+def test_host_transform_tables_match_oracle(hp, p):
+    """The library's reference-element tables (DCT composed with the Chebyshev -> Legendre
+    connection; Legendre values; local basis and derivatives at the points) against the
+    oracle's one-element maps (Legendre Vandermonde solve; basis evaluation)."""
+    from oracle import transforms as otr
+    m = p + 1
+    B1 = obasis.make_basis(1, p, -1.0, 1.0, "neumann")   # local order: hats of vertices 0, 1, then bubbles
+    Fw = hp.hpadi_transform_export(p, 0)
+    Iv = hp.hpadi_transform_export(p, 1)
+    ref_f = otr.values_to_legendre_1d(B1, np.eye(m))
+    ref_i = otr.legendre_to_values_1d(B1, np.eye(m))
+    assert np.abs(Fw - ref_f).max() <= 50 * m * 2.0 ** -53 * max(1.0, np.abs(ref_f).max())
+    # the three-term recurrence in FP64 (the oracle's library routine) drifts by a small multiple of
+    # k eps at degree k (6.5 m eps measured at p = 64 and 128); the library's runs in long double
+    assert np.abs(Iv - ref_i).max() <= 10 * m * 2.0 ** -53
+    assert np.abs(Fw @ Iv - np.eye(m)).max() <= 20 * m * 2.0 ** -53
+    R = (obasis.connection_full(B1) @ obasis.restriction(B1)).toarray()
+    D = (obasis.derivative_full(B1) @ obasis.restriction(B1)).toarray()
+    E = hp.hpadi_transform_export(p, 2)
+    Ed = hp.hpadi_transform_export(p, 3)
+    assert np.abs(E - ref_i @ R).max() <= 4 * m * 2.0 ** -53
+    assert np.abs(Ed - ref_i @ D).max() <= 10 * m * 2.0 ** -53   # D on [-1, 1]: d/dt

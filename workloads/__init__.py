@@ -195,3 +195,20 @@ def constant_rhs(n: int, p: int, value: float = 1.0) -> np.ndarray:
     f = np.zeros((p + 1) * n)
     f[:n] = value
     return f
+
+
+# ---------------------------------------------------------------------------
+# Burgers' equation (Sec. 6): a discontinuous initial condition.
+# ---------------------------------------------------------------------------
+
+def burgers_initial(nx: int, px: int, ny: int, py: int, blocks: int = 3, seed: int = 0) -> np.ndarray:
+    """Piecewise Legendre coefficients ((px+1) nx x (py+1) ny, degree-major) of a piecewise
+    constant u0: blocks x blocks equal tiles of the element mesh (nx and ny divisible by
+    blocks), each with a constant drawn U(-1, 1) (default_rng(seed), row-major over tiles).
+    Only the degree-0 coefficients are nonzero."""
+    if nx % blocks or ny % blocks:
+        raise ValueError("the tiles must be unions of elements")
+    vals = np.random.default_rng(seed).uniform(-1.0, 1.0, (blocks, blocks))
+    F = np.zeros(((px + 1) * nx, (py + 1) * ny))
+    F[:nx, :ny] = np.repeat(np.repeat(vals, nx // blocks, axis=0), ny // blocks, axis=1)
+    return F
