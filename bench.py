@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 
 METRIC = "DOF/s of ADI hp-FEM Poisson at rel err 1e-10: mixed vs FP64; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 # HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # scaled by a copy-kernel calibration; valid only while the kernel sources hash
 # to the value recorded with it.
@@ -326,6 +327,67 @@ def section7_table1(hp, torch, steps=3):
             **out}
 
 
+def transforms_burgers(hp, torch, steps=10, n=64, p=64):
+    """Sec. 6 at n = p = 64 per axis (4160 grid points, N = 4095): the 2D grid transforms
+    (two per-element dense passes each; algorithmic traffic: every input and output entry
+    once per pass, 8 bytes; flops 2 (p+1) per output per pass), and the Burgers IMEX
+    step u_t + u u_x = 0.1 Laplace u, zero Dirichlet, dt = 1e-3, from a discontinuous
+    piecewise-constant u0 on 4 x 4 tiles (ADI tolerance 1e-10, FP64 and mixed)."""
+    import numpy as np
+    import workloads
+    x = hp.Op1D(n, p, -1.0, 1.0, "dirichlet")
+    t = hp.Transform(x, x)
+    m = p + 1
+    V = torch.from_numpy(np.random.default_rng(21).standard_normal((n * m, n * m))).cuda()
+    U = torch.from_numpy(np.random.default_rng(22).standard_normal((x.N, x.N))).cuda()
+    F = torch.empty_like(V)
+    W = torch.empty_like(V)
+    nm = n * m
+    ops = {  # name: (call, entries read and written, flops)
+        "values_to_legendre": (lambda: hp.hpadi_values_to_legendre(t.handle, V, F), 4 * nm * nm, 4 * m * nm * nm),
+        "legendre_to_values": (lambda: hp.hpadi_legendre_to_values(t.handle, F, W), 4 * nm * nm, 4 * m * nm * nm),
+        "q_to_values": (lambda: hp.hpadi_q_to_values(t.handle, 0, U, W), x.N * x.N + 2 * x.N * nm + nm * nm,
+                        2 * m * (x.N * nm + nm * nm)),
+    }
+    out = {}
+    for name, (fn, entries, flops) in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms": ms, "GB_per_s": entries * 8 / (ms * 1e-3) / 1e9,
+                     "fp64_TFLOP_per_s": flops / (ms * 1e-3) / 1e12,
+                     "hbm_frac": entries * 8 / (ms * 1e-3) / HBM_PEAK_GBS / 1e9,
+                     "fp64_frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS}
+    hp.hpadi_legendre_to_values(t.handle, F, W)
+    torch.cuda.synchronize()
+    out["round_trip_rel_err"] = float((W - V).abs().max() / V.abs().max())
+    t.close()
+    F0 = workloads.burgers_initial(n, p, n, p, blocks=4, seed=7)
+    for prec in ("fp64", "mixed"):
+        bu = hp.Burgers(x, x, 0.1, 1e-3, 1e-10, prec)
+        Fd = torch.from_numpy(F0).cuda()
+        bu.step(Fd, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = bu.step(Fd, steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        out[f"burgers_{prec}"] = {"ms_per_step": ms, "J": st.J, "rounds": st.rounds,
+                                  "max_abs_coef": float(Fd.abs().max()), "finite": bool(torch.isfinite(Fd).all())}
+        bu.close()
+    log("transforms: " + ", ".join(f"{k} {v['ms']:.3f} ms ({v['GB_per_s']:.0f} GB/s)" for k, v in out.items()
+                                   if isinstance(v, dict) and "GB_per_s" in v)
+        + f"; burgers step fp64 {out['burgers_fp64']['ms_per_step']:.2f} ms, mixed {out['burgers_mixed']['ms_per_step']:.2f} ms")
+    return {"workload": "grid transforms at n=p=64 (4160 x 4160 points); Burgers u_t + u u_x = 0.1 Laplace u, "
+                        "zero Dirichlet on [-1,1]^2, dt=1e-3, n=p=64, discontinuous u0, ADI tol 1e-10", **out}
+
+
 def batch_solve(hp, torch, steps=3, count=512):
     """512 independent screened-Poisson solves (per axis n in {4..64}, p in {8..128}, N <= 2049,
     omega^2 log-uniform in [1e-2, 1e3], random BC) replayed as one graph; G per instance a
@@ -403,6 +465,8 @@ def main():
                     help="run only the variable-coefficient ADI-PCG/FCG loops at N = 1023 (profiling)")
     ap.add_argument("--only-learned", action="store_true",
                     help="run only the learned-correction training and held-out FCG solves (profiling)")
+    ap.add_argument("--only-transforms", action="store_true",
+                    help="run only the grid transforms and the Burgers steps (profiling)")
     ap.add_argument("--schedules", action="store_true",
                     help="time the mixed solve at N = 4095 / 4097 for several FP32 and FP64 shift-family "
                          "tolerances (one JSON line each)")
@@ -423,6 +487,9 @@ def main():
     from paper_2402_11299_amd import hpadi as hp
     hp.lib()
     torch.cuda.init()
+    if args.only_transforms:
+        print(json.dumps(transforms_burgers(hp, torch, steps=args.steps)), flush=True)
+        return
     if args.only_batch:
         print(json.dumps(batch_solve(hp, torch, steps=args.steps)), flush=True)
         return
@@ -535,6 +602,7 @@ def main():
         out["varcoef_fcg"] = varcoef_fcg(hp, torch)
         out["section7_table1"] = section7_table1(hp, torch)
         out["batch"] = batch_solve(hp, torch)
+        out["transforms_burgers"] = transforms_burgers(hp, torch)
         out["learned_correction"] = learned_fcg(hp, torch)
 
     cpu = None

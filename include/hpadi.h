@@ -179,7 +179,9 @@ int hpadi_load_noalloc(hpadi_plan plan, const double* F_dev, int ldf, double* G_
  * delta the round's correction and U_old the iterate before it, all in the
  * lemma's norm ||V X L^T||_F (M^x = V^T V, M^y = L^T L), is <= tol
  * (stats->est_rel_err).  The bound covers the truncation error of the ADI
- * rounds; FP64 rounding adds its own, below 1e-11 relative in every test.
+ * rounds; FP64 rounding adds its own, below 1e-11 relative in every test, and the
+ * estimate is never below 16 unit roundoffs (1.8e-15): a tolerance below that ends
+ * ENOCONV.
  * stats may be NULL.  ENOCONV if the
  * round limit is reached (U holds the last iterate).  Synchronises the stream
  * in MIXED mode (one scalar read-back per FP64 round). */
@@ -370,7 +372,8 @@ int hpadi_transform_export(int p, int which, double* buf, int len);
 typedef struct hpadi_transform_s* hpadi_transform;
 /* Reference-element tables of both axes on the device, and an intermediate array of
  * max(Nleg_x, N_x) x Nleg_y doubles.  hip_stream: the stream of every call on the handle.
- * The operators are copied. */
+ * The operators are copied.  EINVAL for p > 239 on an axis (a workgroup stages the p + 1
+ * inputs of 64 lines of an element in LDS). */
 int hpadi_transform_create(hpadi_op1d x, hpadi_op1d y, void* hip_stream, hpadi_transform* out);
 /* F = F_x V F_y^T (Sec. 6, the transform F_p on every element along each axis): the
  * piecewise Legendre coefficients (Nleg_x x Nleg_y, degree-major) of the interpolant of

@@ -560,7 +560,7 @@ void plan_free(hpadi_plan_s* P) {
     if (!P) return;
     for (ShiftFamily& F : P->fam) family_free(F);
     for (void* q : {P->Wk, P->Gt, (void*)P->T64, (void*)P->T1, (void*)P->T2, (void*)P->R64,
-                    (void*)P->H, (void*)P->acc})
+                    (void*)P->H, (void*)P->acc, (void*)P->part})
         if (q) hipFree(q);
     if (P->acc_host) hipHostFree(P->acc_host);
     for (auto& r : P->recs) {
@@ -737,13 +737,16 @@ int run_adi(hpadi_plan_s* P, const ShiftFamily& F, int ts, double* U, long ldu, 
 // and ||U*|| >= ||U_new|| - f ||delta|| >= | ||U_old|| - ||delta|| | - f ||delta||.
 // d2 = ||delta||^2, u2 = ||U_old||^2, both in the lemma's norm ||V X L^T||_F.  Returns
 // the bound on ||U* - U_new|| / ||U*|| (infinity when the denominator is not positive).
+// The lemma holds in exact arithmetic; once the correction is rounding noise the bound
+// can fall below what FP64 certifies, so it is never reported below 16 unit roundoffs.
+constexpr double kRoundingFloor = 16.0 * 1.1102230246251565e-16;
 double lemma_bound(double eps, double d2, double u2) {
     const double nd = std::sqrt(std::max(d2, 0.0)), nu = std::sqrt(std::max(u2, 0.0));
     if (!std::isfinite(nd) || !std::isfinite(nu)) return std::numeric_limits<double>::infinity();
-    if (nd == 0.0) return 0.0;
+    if (nd == 0.0) return kRoundingFloor;
     const double f = eps / (1.0 - eps);
     const double lo = std::fabs(nu - nd) - f * nd;
-    return lo > 0.0 ? f * nd / lo : std::numeric_limits<double>::infinity();
+    return lo > 0.0 ? std::max(f * nd / lo, kRoundingFloor) : std::numeric_limits<double>::infinity();
 }
 
 // T1 = U M_y, T2 = U A_y (row operators, FP64).
@@ -797,6 +800,7 @@ int residual_into_r64(hpadi_plan_s* P, const double* G, long ldg, const double* 
     r.wcol = P->dy.dev.mdiag;
     r.U = U;
     r.u_ld = ldu;
+    r.partials = P->part;
     return hpadi::launch_residual(P->dx.dev, r, s) == hipSuccess ? HPADI_OK : HPADI_EHIP;
 }
 
@@ -1253,6 +1257,7 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     bool ok = hipMalloc(&P->Wk, P->nint * 8) == hipSuccess && hipMalloc(&P->Gt, P->nint * 8) == hipSuccess &&
               dmalloc(&P->T64, P->nint) == hipSuccess;
     ok = ok && dmalloc(&P->acc, 8) == hipSuccess && hipHostMalloc((void**)&P->acc_host, 8 * sizeof(double)) == hipSuccess;
+    ok = ok && dmalloc(&P->part, (size_t)hpadi::residual_partials(P->dx.dev, P->dy.op.N)) == hipSuccess;
     if (!ok) { plan_free(P); return HPADI_ENOMEM; }
     (void)Nx;
     (void)Ny;

@@ -78,6 +78,7 @@ struct hpadi_plan_s {
     double* H = nullptr;          // load temporary (Nleg_x x N_y)
     long ldh = 0;
     double* acc = nullptr;        // device accumulators
+    double* part = nullptr;       // per-block partial sums of the residual's norms
     double* acc_host = nullptr;   // pinned host copy
     // measurement
     bool timing = false;

@@ -158,8 +158,11 @@ struct Residual {
     const double* wcol;  // diag of M^y (weights along columns)
     const double* U; long u_ld;  // with T1 = U M_y: <U, M_x U M_y>, the squared norm of U in
                                  // the ADI lemma's norm, into norm_acc[2] (U may be NULL)
+    double* partials;            // residual_partials(dx, ncols) doubles for the per-block sums
+                                 // (summed by a second small kernel), or NULL: atomics
 };
 hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s);
+long residual_partials(const DimDev& dx, int ncols);
 
 // G = scale T_x F T_y^T, two elementwise gather passes (Sec. 3.2).
 hipError_t launch_load(const DimDev& dx, const DimDev& dy, const double* F, long ldf, double* H,

@@ -193,15 +193,20 @@ __device__ __forceinline__ void gather_km(const DimDev& d, const double* x, long
     }
 }
 
-// Row operator: lines are rows (contiguous positions); thread x -> position.
+// Row operator: lines are rows (contiguous positions); thread x -> position, and a block
+// takes kRowLines consecutive lines (fewer, longer workgroups: one line each made the
+// launch dispatch-bound).
+constexpr int kRowLines = 8;
 __global__ void __launch_bounds__(256) op_apply_rows(DimDev d, OpApply a) {
     const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-    const int line = blockIdx.y;
-    if (pos >= d.N || line >= a.nlines) return;
-    double Kx, Mx;
-    gather_km(d, a.in + (long)line * a.in_sl, a.in_sp, pos, Kx, Mx);
-    a.out1[(long)line * a.o1_sl + (long)pos * a.o1_sp] = a.k1 * Kx + a.t1 * Mx;
-    if (a.out2) a.out2[(long)line * a.o2_sl + (long)pos * a.o2_sp] = a.k2 * Kx + a.t2 * Mx;
+    const int l0 = blockIdx.y * kRowLines;
+    if (pos >= d.N) return;
+    for (int line = l0; line < min(l0 + kRowLines, a.nlines); ++line) {
+        double Kx, Mx;
+        gather_km(d, a.in + (long)line * a.in_sl, a.in_sp, pos, Kx, Mx);
+        a.out1[(long)line * a.o1_sl + (long)pos * a.o1_sp] = a.k1 * Kx + a.t1 * Mx;
+        if (a.out2) a.out2[(long)line * a.o2_sl + (long)pos * a.o2_sp] = a.k2 * Kx + a.t2 * Mx;
+    }
 }
 
 // Column operator: lines are columns; thread x -> line (contiguous), y -> position.
@@ -215,51 +220,134 @@ __global__ void __launch_bounds__(256) op_apply_cols(DimDev d, OpApply a) {
     if (a.out2) a.out2[(long)line * a.o2_sl + (long)pos * a.o2_sp] = a.k2 * Kx + a.t2 * Mx;
 }
 
+// The x-direction stencil of K and M at one position as a fixed number of taps (App. A
+// entries): K x = sum_t kc[t] x[idx[t]], M x = sum_t mc[t] x[idx[t]].  Absent taps point at
+// the position itself with zero coefficients, and every choice is a select, not a branch,
+// so that the loads of several positions can be in flight together.  Hat rows have 7 taps
+// (itself, the neighbouring hats, W_0 and W_1 of both adjacent elements), bubble rows 5
+// (itself, degrees m -/+ 2, and for m <= 1 the hats of the element's two vertices).
+template <int NT>
+struct Taps {
+    int idx[NT];
+    double kc[NT], mc[NT];
+};
+
+__device__ __forceinline__ void hat_taps(const DimDev& d, int h, Taps<7>& t) {
+    const int n = d.n, nh = d.nh, p = d.p;
+    const int v = vertex_of_hat(d.bc, h);
+    const bool has_l = v >= 1, has_r = v <= n - 1;
+    const int ql = has_l ? v - 1 : 0, qr = has_r ? v : 0;
+    const double dl = has_l ? d.delta[ql] : 0.0, il = has_l ? d.invdelta[ql] : 0.0;
+    const double dr = has_r ? d.delta[qr] : 0.0, ir = has_r ? d.invdelta[qr] : 0.0;
+    const bool hl = has_l && vertex_is_hat(d.bc, n, v - 1), hr = has_r && vertex_is_hat(d.bc, n, v + 1);
+    t.idx[0] = h;
+    t.kc[0] = il + ir;
+    t.mc[0] = (dl + dr) * (1.0 / 3.0);
+    t.idx[1] = hl ? h - 1 : h;
+    t.kc[1] = hl ? -il : 0.0;
+    t.mc[1] = hl ? dl * (1.0 / 6.0) : 0.0;
+    t.idx[2] = hr ? h + 1 : h;
+    t.kc[2] = hr ? -ir : 0.0;
+    t.mc[2] = hr ? dr * (1.0 / 6.0) : 0.0;
+    const bool w0 = p >= 2, w1 = p >= 3;
+    t.idx[3] = (has_l && w0) ? nh + ql : h;
+    t.mc[3] = (has_l && w0) ? dl * (1.0 / 6.0) : 0.0;
+    t.idx[4] = (has_l && w1) ? nh + n + ql : h;
+    t.mc[4] = (has_l && w1) ? dl * (1.0 / 30.0) : 0.0;
+    t.idx[5] = (has_r && w0) ? nh + qr : h;
+    t.mc[5] = (has_r && w0) ? dr * (1.0 / 6.0) : 0.0;
+    t.idx[6] = (has_r && w1) ? nh + n + qr : h;
+    t.mc[6] = (has_r && w1) ? -dr * (1.0 / 30.0) : 0.0;
+    t.kc[3] = t.kc[4] = t.kc[5] = t.kc[6] = 0.0;
+}
+
+__device__ __forceinline__ void bubble_taps(const DimDev& d, int pos, Taps<5>& t) {
+    const int n = d.n, nh = d.nh, p = d.p;
+    const int b = pos - nh, m = b / n, e = b - m * n;
+    const double de = d.delta[e], ide = d.invdelta[e];
+    const double* kd = d.tab64;
+    const double* md = d.tab64 + d.tabstride;
+    const double* mo = d.tab64 + 2 * d.tabstride;
+    t.idx[0] = pos;
+    t.kc[0] = kd[m] * ide;
+    t.mc[0] = md[m] * de;
+    const bool lo = m >= 2, hi = m + 2 <= p - 2;
+    t.idx[1] = lo ? pos - 2 * n : pos;
+    t.mc[1] = lo ? mo[lo ? m - 2 : 0] * de : 0.0;
+    t.idx[2] = hi ? pos + 2 * n : pos;
+    t.mc[2] = hi ? mo[m] * de : 0.0;
+    const bool hl = m <= 1 && vertex_is_hat(d.bc, n, e), hr = m <= 1 && vertex_is_hat(d.bc, n, e + 1);
+    const double cl = m == 0 ? de * (1.0 / 6.0) : -de * (1.0 / 30.0);
+    const double cr = m == 0 ? de * (1.0 / 6.0) : de * (1.0 / 30.0);
+    t.idx[3] = hl ? hat_of_vertex(d.bc, e) : pos;
+    t.mc[3] = hl ? cl : 0.0;
+    t.idx[4] = hr ? hat_of_vertex(d.bc, e + 1) : pos;
+    t.mc[4] = hr ? cr : 0.0;
+    t.kc[1] = t.kc[2] = t.kc[3] = t.kc[4] = 0.0;
+}
+
+__device__ __forceinline__ void make_taps(const DimDev& d, int pos, Taps<7>& t) { hat_taps(d, pos, t); }
+__device__ __forceinline__ void make_taps(const DimDev& d, int pos, Taps<5>& t) { bubble_taps(d, pos, t); }
+
 // r[i][j] = alpha G[i][j] + beta ((ax_k K + ax_t M) T1 + M T2)[i][j], operators along x.
-__global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
-    // A block owns 256 columns and a contiguous band of rows; a thread takes RU rows at a
-    // time and issues all their loads before any store (the stores may not be reordered
-    // above loads through possibly aliasing pointers), so RU rows of gathers are in
-    // flight at once.  The weighted sums of squares are reduced per block (one atomic
-    // pair per block).
+// A block owns 256 columns and a band of rows, all hats (7-tap rows) or all bubbles (5-tap
+// rows); a thread takes RU rows at a time, whose taps are the same for every lane, and
+// issues all their loads before any store, so that RU rows of gathers are in flight at
+// once.  The weighted sums of squares are reduced per block (one atomic per sum).
+template <int NT>
+__device__ __forceinline__ void residual_rows(const DimDev& dx, const Residual& a, int j, int ibeg, int iend,
+                                              double& sr, double& sg, double& su) {
     constexpr int RU = 4;
+    for (int i0 = ibeg; i0 < iend; i0 += RU) {
+        double rv[RU], gv[RU], uv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int i = min(i0 + u, iend - 1);  // a repeated row past the band end is not stored
+            Taps<NT> t;
+            make_taps(dx, i, t);
+            double K1 = 0.0, M1 = 0.0, M2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const double x1 = a.T1[(long)t.idx[q] * a.t_ld + j];
+                const double x2 = a.T2[(long)t.idx[q] * a.t_ld + j];
+                K1 += t.kc[q] * x1;
+                M1 += t.mc[q] * x1;
+                M2 += t.mc[q] * x2;
+            }
+            gv[u] = a.G ? a.G[(long)i * a.g_ld + j] : 0.0;
+            rv[u] = a.alpha * gv[u] + a.beta * (a.ax_k * K1 + a.ax_t * M1 + M2);
+            uv[u] = a.U ? a.U[(long)i * a.u_ld + j] * M1 : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int i = i0 + u;
+            if (i >= iend) continue;
+            const double r = rv[u], g = gv[u];
+            if (a.r64) a.r64[(long)i * a.r64_ld + j] = r;
+            if (a.r32) a.r32[(long)i * a.r32_ld + j] = (float)r;
+            if (a.norm_acc) {
+                const double w = dx.mdiag[i] * a.wcol[j];
+                sr += w * r * r;
+                sg += w * g * g;
+                su += uv[u];
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     __shared__ double red[3][4];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int rpb = (dx.N + gridDim.y - 1) / gridDim.y;
-    const int ibeg = blockIdx.y * rpb, iend = min(dx.N, ibeg + rpb);
+    // band 0 is the hats; the bubbles are split into gridDim.y - 1 bands
+    const int nb = dx.N - dx.nh, bands = gridDim.y - 1;
     double sr = 0.0, sg = 0.0, su = 0.0;
     if (j < a.ncols) {
-        for (int i0 = ibeg; i0 < iend; i0 += RU) {
-            double rv[RU], gv[RU], uv[RU];
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                const int i = i0 + u;
-                rv[u] = 0.0;
-                gv[u] = 0.0;
-                uv[u] = 0.0;
-                if (i < iend) {
-                    double K1, M1, K2, M2;
-                    gather_km(dx, a.T1 + j, a.t_ld, i, K1, M1);
-                    gather_km(dx, a.T2 + j, a.t_ld, i, K2, M2);
-                    gv[u] = a.G ? a.G[(long)i * a.g_ld + j] : 0.0;
-                    rv[u] = a.alpha * gv[u] + a.beta * (a.ax_k * K1 + a.ax_t * M1 + M2);
-                    if (a.U) uv[u] = a.U[(long)i * a.u_ld + j] * M1;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                const int i = i0 + u;
-                if (i >= iend) continue;
-                const double r = rv[u], g = gv[u];
-                if (a.r64) a.r64[(long)i * a.r64_ld + j] = r;
-                if (a.r32) a.r32[(long)i * a.r32_ld + j] = (float)r;
-                if (a.norm_acc) {
-                    const double w = dx.mdiag[i] * a.wcol[j];
-                    sr += w * r * r;
-                    sg += w * g * g;
-                    su += uv[u];
-                }
-            }
+        if (blockIdx.y == 0) {
+            residual_rows<7>(dx, a, j, 0, dx.nh, sr, sg, su);
+        } else {
+            const int rpb = (nb + bands - 1) / bands;
+            const int ibeg = dx.nh + (blockIdx.y - 1) * rpb, iend = min(dx.N, ibeg + rpb);
+            residual_rows<5>(dx, a, j, ibeg, iend, sr, sg, su);
         }
     }
     if (a.norm_acc) {
@@ -273,11 +361,33 @@ __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
             red[2][w] = su;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            atomicAdd(a.norm_acc + 0, red[0][0] + red[0][1] + red[0][2] + red[0][3]);
-            atomicAdd(a.norm_acc + 1, red[1][0] + red[1][1] + red[1][2] + red[1][3]);
-            if (a.U) atomicAdd(a.norm_acc + 2, red[2][0] + red[2][1] + red[2][2] + red[2][3]);
+        if (threadIdx.x < 3) {
+            const int k = threadIdx.x;
+            const double t = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+            if (a.partials) {
+                // one slot per block, summed by residual_reduce (thousands of same-address
+                // atomics serialise at the L2 and dominated the kernel's time)
+                const int nblk = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+                a.partials[(long)k * nblk + b] = t;
+            } else if (k < 2 || a.U) {
+                atomicAdd(a.norm_acc + k, t);
+            }
         }
+    }
+}
+
+// norm_acc[k] += sum of the residual's per-block partial sums k (one workgroup, fixed order).
+__global__ void __launch_bounds__(256) residual_reduce(const double* __restrict__ partials, int nblk, int nk,
+                                                       double* norm_acc) {
+    __shared__ double red[4];
+    for (int k = 0; k < nk; ++k) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) t += partials[(long)k * nblk + b];
+        t = wave_sum(t);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) norm_acc[k] += red[0] + red[1] + red[2] + red[3];
+        __syncthreads();
     }
 }
 
@@ -365,14 +475,31 @@ hipError_t launch_op_apply(const DimDev& d, const OpApply& a, bool column, hipSt
     if (column)
         hipLaunchKernelGGL(op_apply_cols, grid2(a.nlines, d.N), dim3(256), 0, s, d, a);
     else
-        hipLaunchKernelGGL(op_apply_rows, grid2(d.N, a.nlines), dim3(256), 0, s, d, a);
+        hipLaunchKernelGGL(op_apply_rows, grid2(d.N, (a.nlines + kRowLines - 1) / kRowLines), dim3(256), 0, s, d,
+                           a);
     return hipGetLastError();
+}
+
+// One band of hat rows, then bands of about 32 bubble rows; 256 columns per block.
+static dim3 residual_grid(const DimDev& dx, int ncols) {
+    const int nb = dx.N - dx.nh;
+    const int bands = nb <= 0 ? 0 : (nb + 31) / 32;
+    return dim3((unsigned)((ncols + 255) / 256), (unsigned)(1 + bands));
+}
+
+long residual_partials(const DimDev& dx, int ncols) {
+    const dim3 g = residual_grid(dx, ncols);
+    return 3L * g.x * g.y;
 }
 
 hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s) {
     if (a.ncols <= 0 || dx.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(residual_kernel, dim3((a.ncols + 255) / 256, dx.N < 128 ? dx.N : 128), dim3(256), 0, s, dx,
-                       a);
+    const dim3 g = residual_grid(dx, a.ncols);
+    hipLaunchKernelGGL(residual_kernel, g, dim3(256), 0, s, dx, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.norm_acc || !a.partials) return e;
+    hipLaunchKernelGGL(residual_reduce, dim3(1), dim3(256), 0, s, a.partials, (int)(g.x * g.y), a.U ? 3 : 2,
+                       a.norm_acc);
     return hipGetLastError();
 }
 

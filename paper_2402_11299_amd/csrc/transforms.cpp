@@ -111,23 +111,23 @@ std::vector<double> local_basis_matrix(int p, bool deriv) {
     return E;
 }
 
-// Chunked, transposed copy for the device passes: out[(c L + l) rb + k] = mat[c rb + k][l].
-std::vector<double> chunked(const std::vector<double>& mat, int M, int L, int rb) {
-    const int nchunks = (M + rb - 1) / rb;
-    std::vector<double> out((size_t)nchunks * L * rb, 0.0);
-    for (int c = 0; c < nchunks; ++c)
-        for (int l = 0; l < L; ++l)
-            for (int k = 0; k < rb; ++k) {
-                const int i = c * rb + k;
-                if (i < M) out[((size_t)c * L + l) * rb + k] = mat[(size_t)i * L + l];
+// The matrix (M x L, row-major) as matrix-core operand fragments for the device passes:
+// out[((w S + s) 64 + lane)] = mat[16 w + lane % 16][4 s + lane / 16], zero outside.
+std::vector<double> fragments(const std::vector<double>& mat, int M, int L) {
+    const int W = (M + 15) / 16, S = (L + 3) / 4;
+    std::vector<double> out((size_t)W * S * 64, 0.0);
+    for (int w = 0; w < W; ++w)
+        for (int s = 0; s < S; ++s)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int i = 16 * w + lane % 16, l = 4 * s + lane / 16;
+                if (i < M && l < L) out[((size_t)w * S + s) * 64 + lane] = mat[(size_t)i * L + l];
             }
     return out;
 }
 
 struct TrAxis {
     int n = 0, p = 0, m = 0, nh = 0, N = 0, bc = 0;
-    int rb = 0, nchunks = 0;
-    double* fwd = nullptr;   // device tables in the chunked layout
+    double* fwd = nullptr;   // device tables in the fragment layout
     double* inv = nullptr;
     double* ev = nullptr;
     double* dv = nullptr;
@@ -156,15 +156,13 @@ struct hpadi_transform_s {
     }
     int make_axis(const hpadi_op1d_s& op, TrAxis& a) {
         a.n = op.n; a.p = op.p; a.m = op.p + 1; a.nh = op.nh; a.N = op.N; a.bc = op.bc;
-        a.rb = hpadi::elem_chunk(a.m);
-        a.nchunks = (a.m + a.rb - 1) / a.rb;
         std::vector<double> tod(op.n);
         for (int e = 0; e < op.n; ++e) tod[e] = 2.0 / op.delta[e];
         int rc;
-        if ((rc = upload(chunked(forward_matrix(a.p), a.m, a.m, a.rb), &a.fwd)) ||
-            (rc = upload(chunked(inverse_matrix(a.p), a.m, a.m, a.rb), &a.inv)) ||
-            (rc = upload(chunked(local_basis_matrix(a.p, false), a.m, a.m, a.rb), &a.ev)) ||
-            (rc = upload(chunked(local_basis_matrix(a.p, true), a.m, a.m, a.rb), &a.dv)) ||
+        if ((rc = upload(fragments(forward_matrix(a.p), a.m, a.m), &a.fwd)) ||
+            (rc = upload(fragments(inverse_matrix(a.p), a.m, a.m), &a.inv)) ||
+            (rc = upload(fragments(local_basis_matrix(a.p, false), a.m, a.m), &a.ev)) ||
+            (rc = upload(fragments(local_basis_matrix(a.p, true), a.m, a.m), &a.dv)) ||
             (rc = upload(tod, &a.two_over_delta)))
             return rc;
         return HPADI_OK;
@@ -182,8 +180,8 @@ hpadi::ElemPass make_pass(const TrAxis& a, int lin, int lout, const double* tab,
     e.aout = axis_map(a, lout);
     e.L = a.m;  // m points, p + 1 degrees, p + 1 local basis functions
     e.M = a.m;
-    e.rb = a.rb;
-    e.nchunks = a.nchunks;
+    e.nwaves = (a.m + 15) / 16;
+    e.ksteps = (a.m + 3) / 4;
     e.tab = tab;
     e.lines = lines;
     return e;
@@ -243,7 +241,7 @@ int hpadi_transform_export(int p, int which, double* buf, int len) {
 int hpadi_transform_create(hpadi_op1d x, hpadi_op1d y, void* hip_stream, hpadi_transform* out) {
     if (!out) return HPADI_EINVAL;
     *out = nullptr;
-    if (!x || !y) return HPADI_EINVAL;
+    if (!x || !y || x->p + 1 > hpadi::elem_max_outputs() || y->p + 1 > hpadi::elem_max_outputs()) return HPADI_EINVAL;
     hpadi_transform_s* T = new (std::nothrow) hpadi_transform_s();
     if (!T) return HPADI_ENOMEM;
     T->stream = (hipStream_t)hip_stream;

@@ -23,16 +23,19 @@ struct AxisMap {
 };
 
 // out[line, o(e, i)] = s_e sum_l Mat[i][l] in[line, g(e, l)] along one axis of a
-// row-major array, for every element e and output i < M.  The matrix is stored in
-// chunks of RB outputs, transposed within a chunk: tab[(c L + l) RB + k] = Mat[c RB + k][l]
-// (rows past M zero).  With tab2 set (Burgers epilogue, row passes only) a second matrix
-// scaled per element by scale2[e] gives w = tab2 . in, and the pass stores v - dt w v.
+// row-major array, for every element e and output i < M.  The matrix is stored as the A
+// operands of v_mfma_f64_16x16x4f64: tab[((w S + s) 64 + lane)] = Mat[16 w + lane % 16]
+// [4 s + lane / 16] (zero outside M x L), w < nwaves = ceil(M / 16), s < ksteps = ceil(L / 4).
+// A workgroup of nwaves waves stages the inputs of 64 lines in LDS (max(4 ksteps, 16 nwaves)
+// x 80 doubles, at most 160 KiB).  With tab2 set (Burgers epilogue, row passes only) a
+// second matrix scaled per element by scale2[e] gives w = tab2 . in, and the pass stores
+// v - dt w v.
 struct ElemPass {
     const double* in; long ldin;
     double* out; long ldout;
     AxisMap ain, aout;
     int L, M;              // inputs and outputs per element
-    int rb, nchunks;       // chunk size (the kernel's RB) and count
+    int nwaves, ksteps;    // ceil(M / 16), ceil(L / 4)
     const double* tab;
     const double* tab2;    // or NULL
     const double* scale;   // per-element factor of tab (NULL = 1)
@@ -41,8 +44,8 @@ struct ElemPass {
     int lines;             // independent lines: columns (row pass) or rows (column pass)
 };
 
-// Chunk size of the passes for M outputs per element (8, 16 or 33).
-int elem_chunk(int M);
+// The largest M and L a pass takes (the LDS tile bounds them).
+int elem_max_outputs();
 // Row pass: the transformed axis is x (array rows); lines are columns.
 hipError_t launch_elem_rows(const ElemPass& a, hipStream_t s);
 // Column pass: the transformed axis is y (array columns); lines are rows.  No tab2.

@@ -5,13 +5,14 @@
 // elements (the reference-element transform, or the evaluation of the local basis or of its
 // derivative at the reference points).  One pass applies such a matrix along x (a row pass:
 // every column of the array is an independent line) or along y (a column pass: every row
-// is one).  A lane owns one line of one element and keeps a chunk of up to RB outputs in
-// registers; the matrix entries are the same for every lane of the workgroup and come
-// through the scalar cache, so the inner loop is one vector load and RB FMAs per input.
-// Row passes read and write whole rows (coalesced); column passes have the lanes of a wave
-// on consecutive elements of a row, which makes Legendre- and Q-ordered accesses contiguous
-// and leaves the element-major value accesses strided by the points per element (their
-// cache lines are used over consecutive inputs).  FP64 throughout.
+// is one).  Per workgroup and element this is a small dense product, out (M x 64 lines) =
+// Mat (M x L) . in (L x 64 lines), run on the matrix cores in FP64
+// (v_mfma_f64_16x16x4f64): the inputs of 64 lines are staged in LDS with coalesced loads,
+// wave w owns the output rows 16 w .. 16 w + 15 and streams its fragments of Mat from a
+// precomputed fragment-ordered table (L2-resident), four 16 x 16 accumulator tiles cover
+// the 64 lines.  On MI355X the FP64 matrix rate equals the FP64 vector rate; the matrix
+// cores are used because they take both operands from registers, where a vector FMA
+// kernel would need one table entry per FMA broadcast through the scalar cache.
 //
 // The paper composes a DCT with a fast Chebyshev-Legendre transform; at the degrees used
 // here (p <= 128) the dense per-element product costs 2 (p+1) flops per output, about what
@@ -34,136 +35,228 @@ __device__ __forceinline__ int local_index(const AxisMap& a, int e, int l) {
     return v;
 }
 
-// Block b of a launch of 8 k nchunks workgroups along x: the nchunks chunks of one tile
-// run on one XCD (workgroups are dealt to the 8 XCDs round robin), so a tile's input is
-// read from HBM once and reused from that XCD's L2.
-__device__ __forceinline__ void tile_and_chunk(int nchunks, int& tile, int& chunk) {
-    const int b = blockIdx.x;
-    const int slot = b >> 3;
-    chunk = slot % nchunks;
-    tile = (slot / nchunks) * 8 + (b & 7);
-}
 
-template <int RB, bool BURG>
-__global__ void __launch_bounds__(256) elem_rows_kernel(ElemPass a, int ntiles) {
-    int tile, chunk;
-    tile_and_chunk(a.nchunks, tile, chunk);
-    if (tile >= ntiles) return;
-    const int e = blockIdx.y;
-    const int c = tile * 256 + threadIdx.x;
-    const bool act = c < a.lines;
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kLines = 64;     // lines per workgroup
+constexpr int kStride = 65;    // LDS row stride (doubles): odd, so that walking a tile column
+                               // (consecutive l of one line) spreads over the banks
+constexpr int kBatch = 16;     // loads in flight per thread while staging
+constexpr int kMaxKsteps = 60; // L <= 240
+
+// Column passes: the 64 items of a workgroup are R rows x E consecutive elements.
+__device__ __forceinline__ int col_tile_E(int n) { return n < kLines ? n : kLines; }
+
+// Accumulator layout of v_mfma_f64_16x16x4f64 (checked on the device): register r of lane
+// holds row (lane / 16) + 4 r, column lane % 16; operand A is read at (lane % 16, lane / 16)
+// and B at (lane / 16, lane % 16).
+template <int KS, bool ROWS, bool BURG>
+__global__ void __launch_bounds__(1024) elem_pass_kernel(ElemPass a) {
+    extern __shared__ double tile[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nt = blockDim.x;
+    const int L = a.L, S = a.ksteps, Lpad = 4 * S;
     const double* __restrict__ in = a.in;
-    const double* __restrict__ tab = a.tab + (long)chunk * a.L * RB;
-    const double* __restrict__ tab2 = BURG ? a.tab2 + (long)chunk * a.L * RB : nullptr;
-    double acc[RB], acc2[BURG ? RB : 1];
-#pragma unroll
-    for (int k = 0; k < RB; ++k) acc[k] = 0.0;
-    if (BURG) {
-#pragma unroll
-        for (int k = 0; k < RB; ++k) acc2[k] = 0.0;
+    int e = 0, c0 = 0, r0 = 0, e0 = 0, En = 0, E = 1, rows = 0;
+    if (ROWS) {
+        e = blockIdx.y;
+        c0 = blockIdx.x * kLines;
+    } else {
+        E = col_tile_E(a.ain.n);
+        const int R = kLines / E;
+        e0 = blockIdx.y * E;
+        En = min(E, a.ain.n - e0);
+        r0 = blockIdx.x * R;
+        rows = min(R, a.lines - r0);
     }
-    for (int l = 0; l < a.L; ++l) {
-        const int r = local_index(a.ain, e, l);
-        double x = 0.0;
-        if (r >= 0 && act) x = in[(long)r * a.ldin + c];
-        const double* t = tab + l * RB;
+    // ---- stage the inputs: tile[l][line], rows L..Lpad-1 zero
+    int total;
+    if (ROWS) total = L * kLines;
+    else total = rows * En * L;
+    for (int base = threadIdx.x; base < total; base += nt * kBatch) {
+        double v[kBatch];
+        int dst[kBatch];
 #pragma unroll
-        for (int k = 0; k < RB; ++k) acc[k] = fma(t[k], x, acc[k]);
-        if (BURG) {
-            const double* t2 = tab2 + l * RB;
+        for (int b = 0; b < kBatch; ++b) {
+            const int idx = base + b * nt;
+            v[b] = 0.0;
+            dst[b] = -1;
+            if (idx < total) {
+                long src = -1;
+                if (ROWS) {
+                    const int l = idx >> 6, j = idx & 63;
+                    const int r = local_index(a.ain, e, l);
+                    dst[b] = l * kStride + j;
+                    if (r >= 0 && c0 + j < a.lines) src = (long)r * a.ldin + c0 + j;
+                } else if (a.ain.layout == AX_VALUES) {
+                    // a row's segment of En elements is contiguous: walk it in address order
+                    const int seg = En * L;
+                    const int rl = idx / seg, rem = idx - rl * seg;
+                    const int el = rem / L, l = rem - el * L;
+                    dst[b] = l * kStride + rl * E + el;
+                    src = (long)(r0 + rl) * a.ldin + (long)(e0 + el) * L + l;
+                } else {
+                    // degree- or basis-major: consecutive elements are contiguous for a fixed l
+                    const int el = idx % En, t = idx / En;
+                    const int l = t % L, rl = t / L;
+                    const int gi = local_index(a.ain, e0 + el, l);
+                    dst[b] = l * kStride + rl * E + el;
+                    if (gi >= 0) src = (long)(r0 + rl) * a.ldin + gi;
+                }
+                if (src >= 0) v[b] = in[src];
+            }
+        }
 #pragma unroll
-            for (int k = 0; k < RB; ++k) acc2[k] = fma(t2[k], x, acc2[k]);
+        for (int b = 0; b < kBatch; ++b)
+            if (dst[b] >= 0) tile[dst[b]] = v[b];
+    }
+    // the padded rows L..Lpad-1 meet zero table entries and must hold finite values (lines
+    // past a tile's items only feed their own, unstored, output columns)
+    for (int idx = threadIdx.x; idx < (Lpad - L) * kLines; idx += nt)
+        tile[(L + (idx >> 6)) * kStride + (idx & 63)] = 0.0;
+    __syncthreads();
+    // ---- rows 16 w .. 16 w + 15 of the outputs for the 64 lines
+    const int kr = lane >> 4, jc = lane & 15;
+    // this wave's operand fragments of the matrix: in registers for the whole product when
+    // KS > 0 (the loop is unrolled), else streamed from the L2-resident table
+    const double* __restrict__ tf = a.tab + (long)w * S * 64 + lane;
+    const double* __restrict__ tf2 = BURG ? a.tab2 + (long)w * S * 64 + lane : nullptr;
+    double4_t acc[4], acc2[BURG ? 4 : 1];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        acc[ct] = double4_t{0.0, 0.0, 0.0, 0.0};
+        if (BURG) acc2[ct] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
+    if (KS > 0) {
+        double af[KS > 0 ? KS : 1];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) af[s] = s < S ? tf[s * 64] : 0.0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (s < S) {  // uniform
+                const double* brow = tile + (4 * s + kr) * kStride + jc;
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s], brow[16 * ct], acc[ct], 0, 0, 0);
+            }
+        }
+    } else {
+        for (int s = 0; s < S; ++s) {
+            const double av = tf[s * 64];
+            const double av2 = BURG ? tf2[s * 64] : 0.0;
+            const double* brow = tile + (4 * s + kr) * kStride + jc;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const double bv = brow[16 * ct];
+                acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+                if (BURG) acc2[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av2, bv, acc2[ct], 0, 0, 0);
+            }
         }
     }
-    if (!act) return;
-    const double s = a.scale ? a.scale[e] : 1.0;
-    const double s2 = BURG ? a.scale2[e] : 0.0;
+    // ---- results: output row i = 16 w + kr + 4 r, line 16 ct + jc
+    if (ROWS) {
+        const double sc = a.scale ? a.scale[e] : 1.0;
+        const double s2 = BURG ? a.scale2[e] : 0.0;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) {
-        const int i = chunk * RB + k;
-        if (i < a.M) {
-            double v = acc[k] * s;
-            if (BURG) v = v - a.dt * (acc2[k] * s2) * v;
-            a.out[(long)local_index(a.aout, e, i) * a.ldout + c] = v;
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + kr + 4 * r;
+            if (i >= a.M) continue;
+            double* orow = a.out + (long)local_index(a.aout, e, i) * a.ldout + c0;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const int j = 16 * ct + jc;
+                if (c0 + j >= a.lines) continue;
+                double v = acc[ct][r] * sc;
+                if (BURG) v = v - a.dt * (acc2[ct][r] * s2) * v;
+                orow[j] = v;
+            }
         }
+        return;
+    }
+    if (a.aout.layout != AX_VALUES) {
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int j = 16 * ct + jc;
+            const int rl = j / E, el = j - rl * E;
+            if (rl >= rows || el >= En) continue;
+            const double sc = a.scale ? a.scale[e0 + el] : 1.0;
+            double* orow = a.out + (long)(r0 + rl) * a.ldout;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * w + kr + 4 * r;
+                if (i < a.M) orow[local_index(a.aout, e0 + el, i)] = acc[ct][r] * sc;
+            }
+        }
+        return;
+    }
+    // element-major outputs: through the tile, then stored in address order
+    __syncthreads();  // every wave has read its inputs
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int j = 16 * ct + jc;
+        const int rl = j / E, el = j - rl * E;
+        const double sc = (a.scale && rl < rows && el < En) ? a.scale[e0 + el] : 1.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + kr + 4 * r;
+            if (i < a.M) tile[i * kStride + j] = acc[ct][r] * sc;
+        }
+    }
+    __syncthreads();
+    const int M = a.M, seg = En * M;
+    for (int idx = threadIdx.x; idx < rows * seg; idx += nt) {
+        const int rl = idx / seg, rem = idx - rl * seg;
+        const int el = rem / M, i = rem - el * M;
+        a.out[(long)(r0 + rl) * a.ldout + (long)(e0 + el) * M + i] = tile[i * kStride + rl * E + el];
     }
 }
 
-template <int RB>
-__global__ void __launch_bounds__(256) elem_cols_kernel(ElemPass a, int ntiles) {
-    int tile, chunk;
-    tile_and_chunk(a.nchunks, tile, chunk);
-    if (tile >= ntiles) return;
+size_t pass_lds(const ElemPass& a) {
+    const int rows = 4 * a.ksteps > 16 * a.nwaves ? 4 * a.ksteps : 16 * a.nwaves;
+    return (size_t)rows * kStride * sizeof(double);
+}
+
+template <int KS, bool ROWS>
+hipError_t launch_ks(const ElemPass& a, hipStream_t s) {
     const int n = a.ain.n;
-    const long item = (long)tile * 256 + threadIdx.x;
-    const long r = item / n;
-    const int e = (int)(item - r * n);
-    const bool act = r < a.lines;
-    const double* __restrict__ row = a.in + (act ? r : 0) * a.ldin;
-    const double* __restrict__ tab = a.tab + (long)chunk * a.L * RB;
-    double acc[RB];
-#pragma unroll
-    for (int k = 0; k < RB; ++k) acc[k] = 0.0;
-    for (int l = 0; l < a.L; ++l) {
-        const int idx = local_index(a.ain, e, l);
-        const double x = (idx >= 0 && act) ? row[idx] : 0.0;
-        const double* t = tab + l * RB;
-#pragma unroll
-        for (int k = 0; k < RB; ++k) acc[k] = fma(t[k], x, acc[k]);
+    dim3 grid;
+    if (ROWS) {
+        grid = dim3((unsigned)((a.lines + kLines - 1) / kLines), (unsigned)n);
+    } else {
+        const int E = n < kLines ? n : kLines, R = kLines / E;
+        grid = dim3((unsigned)((a.lines + R - 1) / R), (unsigned)((n + E - 1) / E));
     }
-    if (!act) return;
-    const double s = a.scale ? a.scale[e] : 1.0;
-    double* orow = a.out + r * a.ldout;
-#pragma unroll
-    for (int k = 0; k < RB; ++k) {
-        const int i = chunk * RB + k;
-        if (i < a.M) orow[local_index(a.aout, e, i)] = acc[k] * s;
-    }
-}
-
-template <int RB>
-hipError_t rows_rb(const ElemPass& a, hipStream_t s) {
-    const int ntiles = (a.lines + 255) / 256;
-    const dim3 grid((unsigned)((ntiles + 7) / 8 * 8 * a.nchunks), (unsigned)a.ain.n);
-    if (a.tab2)
-        hipLaunchKernelGGL((elem_rows_kernel<RB, true>), grid, dim3(256), 0, s, a, ntiles);
+    const dim3 block((unsigned)(64 * a.nwaves));
+    if (ROWS && a.tab2)  // two products: fragments streamed (registers would spill)
+        hipLaunchKernelGGL((elem_pass_kernel<0, true, true>), grid, block, pass_lds(a), s, a);
+    else if (ROWS)
+        hipLaunchKernelGGL((elem_pass_kernel<KS, true, false>), grid, block, pass_lds(a), s, a);
     else
-        hipLaunchKernelGGL((elem_rows_kernel<RB, false>), grid, dim3(256), 0, s, a, ntiles);
+        hipLaunchKernelGGL((elem_pass_kernel<KS, false, false>), grid, block, pass_lds(a), s, a);
     return hipGetLastError();
 }
 
-template <int RB>
-hipError_t cols_rb(const ElemPass& a, hipStream_t s) {
-    const long items = (long)a.lines * a.ain.n;
-    const int ntiles = (int)((items + 255) / 256);
-    const dim3 grid((unsigned)((ntiles + 7) / 8 * 8 * a.nchunks));
-    hipLaunchKernelGGL((elem_cols_kernel<RB>), grid, dim3(256), 0, s, a, ntiles);
-    return hipGetLastError();
+template <bool ROWS>
+hipError_t launch_pass(const ElemPass& a, hipStream_t s) {
+    if (a.lines <= 0 || a.ain.n <= 0) return hipSuccess;
+    if ((!ROWS && a.tab2) || a.nwaves < 1 || 16 * a.nwaves < a.M || a.nwaves > 16 || a.ksteps < 1 ||
+        4 * a.ksteps < a.L || a.ksteps > kMaxKsteps || pass_lds(a) > 160 * 1024 || a.ain.n != a.aout.n)
+        return hipErrorInvalidValue;
+    // the k-steps of the product, rounded up to a compiled count (fragments in registers),
+    // or streamed beyond 33
+    if (a.ksteps <= 4) return launch_ks<4, ROWS>(a, s);
+    if (a.ksteps <= 9) return launch_ks<9, ROWS>(a, s);
+    if (a.ksteps <= 17) return launch_ks<17, ROWS>(a, s);
+    if (a.ksteps <= 33) return launch_ks<33, ROWS>(a, s);
+    return launch_ks<0, ROWS>(a, s);
 }
 
 }  // namespace
 
-int elem_chunk(int M) { return M <= 8 ? 8 : (M <= 16 ? 16 : 33); }
+int elem_max_outputs() { return 240; }
 
-hipError_t launch_elem_rows(const ElemPass& a, hipStream_t s) {
-    if (a.lines <= 0 || a.ain.n <= 0) return hipSuccess;
-    switch (a.rb) {
-        case 8: return rows_rb<8>(a, s);
-        case 16: return rows_rb<16>(a, s);
-        case 33: return rows_rb<33>(a, s);
-        default: return hipErrorInvalidValue;
-    }
-}
+hipError_t launch_elem_rows(const ElemPass& a, hipStream_t s) { return launch_pass<true>(a, s); }
 
-hipError_t launch_elem_cols(const ElemPass& a, hipStream_t s) {
-    if (a.lines <= 0 || a.ain.n <= 0) return hipSuccess;
-    if (a.tab2) return hipErrorInvalidValue;
-    switch (a.rb) {
-        case 8: return cols_rb<8>(a, s);
-        case 16: return cols_rb<16>(a, s);
-        case 33: return cols_rb<33>(a, s);
-        default: return hipErrorInvalidValue;
-    }
-}
+hipError_t launch_elem_cols(const ElemPass& a, hipStream_t s) { return launch_pass<false>(a, s); }
 
 }  // namespace hpadi
