@@ -38,9 +38,19 @@ def load(opx: Operators1D, opy: Operators1D, F: np.ndarray) -> np.ndarray:
     return np.asarray(opx.T @ (opy.T @ np.asarray(F).T).T)
 
 
-def apply_operator(opx: Operators1D, opy: Operators1D, omega2: float, U: np.ndarray) -> np.ndarray:
-    """A_Y^x U M^y + M^x U A_Y^y."""
-    Ax, Ay = opx.A(omega2), opy.A(omega2)
+def axis_operators(opx: Operators1D, opy: Operators1D, omega2: float, coef=None):
+    """(A_x, A_y): A_Y of both axes, or with coef = (kx, sx, ky, sy) the general pair
+    A_x = kx K_x + sx M_x, A_y = ky K_y + sy M_y, i.e. Alg. 2's A U C - D U B = F with
+    A = A_x, D = M_x, C = M_y, B = -A_y (anisotropic or unequally screened problems)."""
+    if coef is None:
+        return opx.A(omega2), opy.A(omega2)
+    kx, sx, ky, sy = coef
+    return (kx * opx.K + sx * opx.M).tocsr(), (ky * opy.K + sy * opy.M).tocsr()
+
+
+def apply_operator(opx: Operators1D, opy: Operators1D, omega2: float, U: np.ndarray, coef=None) -> np.ndarray:
+    """A_Y^x U M^y + M^x U A_Y^y (or A_x U M^y + M^x U A_y with coef)."""
+    Ax, Ay = axis_operators(opx, opy, omega2, coef)
     UMy = (opy.M @ U.T).T
     UAy = (Ay @ U.T).T
     return np.asarray(Ax @ UMy + opx.M @ UAy)
@@ -58,9 +68,9 @@ def rel_l2_error(U: np.ndarray, Uref: np.ndarray, opx: Operators1D, opy: Operato
 # Exact references.
 # --------------------------------------------------------------------------
 
-def solve_dense(opx: Operators1D, opy: Operators1D, omega2: float, G: np.ndarray) -> np.ndarray:
+def solve_dense(opx: Operators1D, opy: Operators1D, omega2: float, G: np.ndarray, coef=None) -> np.ndarray:
     """Dense Kronecker solve (A_Y^x (x) M^y + M^x (x) A_Y^y) vec_r(U) = vec_r(G) (small N)."""
-    Ax, Ay = opx.A(omega2).toarray(), opy.A(omega2).toarray()
+    Ax, Ay = (A.toarray() for A in axis_operators(opx, opy, omega2, coef))
     Mx, My = opx.M.toarray(), opy.M.toarray()
     Op = np.kron(Ax, My) + np.kron(Mx, Ay)
     u = np.linalg.solve(Op, np.asarray(G).reshape(-1))
@@ -68,19 +78,20 @@ def solve_dense(opx: Operators1D, opy: Operators1D, omega2: float, G: np.ndarray
 
 
 def solve_fdm(opx: Operators1D, opy: Operators1D, omega2: float, G: np.ndarray,
-              refine: int = 1) -> np.ndarray:
+              refine: int = 1, coef=None) -> np.ndarray:
     """Fast diagonalisation (Lynch et al. 1964, cited in Sec. 1): A_Y V = M V Lambda
     per dimension (library eigensolver), U = V_x [(V_x^T G V_y) / (lx_i + ly_j)] V_y^T,
     followed by ``refine`` FP64 residual-correction steps."""
-    lx, Vx = sla.eigh(opx.A(omega2).toarray(), opx.M.toarray())
-    ly, Vy = sla.eigh(opy.A(omega2).toarray(), opy.M.toarray())
+    Ax, Ay = axis_operators(opx, opy, omega2, coef)
+    lx, Vx = sla.eigh(Ax.toarray(), opx.M.toarray())
+    ly, Vy = sla.eigh(Ay.toarray(), opy.M.toarray())
     den = lx[:, None] + ly[None, :]
 
     def inv(R):
         return Vx @ ((Vx.T @ R @ Vy) / den) @ Vy.T
     U = inv(G)
     for _ in range(refine):
-        U = U + inv(G - apply_operator(opx, opy, omega2, U))
+        U = U + inv(G - apply_operator(opx, opy, omega2, U, coef))
     return U
 
 
@@ -92,16 +103,17 @@ class ADIPlan:
     """Precomputation of Alg. 2 for A = A_Y^x, D = M^x, C = M^y, B = -A_Y^y."""
 
     def __init__(self, opx: Operators1D, opy: Operators1D, omega2: float, eps: float,
-                 interval=None, J=None):
+                 interval=None, J=None, coef=None):
         self.opx, self.opy, self.omega2, self.eps = opx, opy, omega2, eps
+        kx, sx, ky, sy = coef if coef is not None else (1.0, omega2 / 2.0, 1.0, omega2 / 2.0)
         if interval is None:
-            ax, bx = _spectrum.interval(opx, omega2)
-            ay, by = _spectrum.interval(opy, omega2)
+            ax, bx = _spectrum.interval(opx, omega2, kx, sx)
+            ay, by = _spectrum.interval(opy, omega2, ky, sy)
             interval = (ax, bx, -by, -ay)
         self.interval = tuple(float(v) for v in interval)
         a, b, c, d = self.interval
         self.J, self.p, self.q = _shifts.adi_shifts(a, b, c, d, eps, J=J)
-        Ax, Ay = opx.A(omega2), opy.A(omega2)
+        Ax, Ay = axis_operators(opx, opy, omega2, coef)
         # reverse Cholesky of A - q_j D and of -(B - p_j C) = A_Y^y + p_j M^y
         self.fx = [factor_arrowhead(Ax - qj * opx.M, opx.basis) for qj in self.q]
         self.fy = [factor_arrowhead(Ay + pj * opy.M, opy.basis) for pj in self.p]
@@ -128,5 +140,5 @@ class ADIPlan:
         return (U, hist) if return_history else U
 
 
-def solve_adi(opx, opy, omega2, G, eps, interval=None):
-    return ADIPlan(opx, opy, omega2, eps, interval=interval).solve(G)
+def solve_adi(opx, opy, omega2, G, eps, interval=None, coef=None):
+    return ADIPlan(opx, opy, omega2, eps, interval=interval, coef=coef).solve(G)

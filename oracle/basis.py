@@ -15,7 +15,11 @@ Follows Sec. 2 of the paper ("Integrated Legendre functions") and App. A
 * mass M = R^T M_P R, weak Laplacian K = D^T M_P D and load T = R^T M_P
   (Sec. 2.2.1-2.2.2, Sec. 3.1);
 * Dirichlet restriction: drop the first and last hat (Sec. 2.3, P_D);
-  Neumann keeps the full basis C (Sec. 3.3, Sec. 5 "Y = C").
+  Neumann keeps the full basis C (Sec. 3.3, Sec. 5 "Y = C");
+* general boundary conditions (Sec. 3.3): each end is Dirichlet (its hat
+  dropped), Neumann (its hat kept) or Robin alpha u + du/dn = 0 (its hat kept
+  and alpha <v, u> at that end added to the weak Laplacian; Neumann is alpha = 0).
+  Mixed conditions choose the kind per end.
 
 Index conventions (0-based, n elements, degree p):
   hats      Dirichlet: vertices 1..n-1 -> 0..n-2;  Neumann: vertices 0..n -> 0..n
@@ -43,15 +47,22 @@ import scipy.special as ss
 
 DIRICHLET = "dirichlet"
 NEUMANN = "neumann"
+ROBIN = "robin"
 
 
 @dataclasses.dataclass(frozen=True)
 class Basis1D:
-    """A 1D mesh x_0 < ... < x_n with degree p and a boundary condition."""
+    """A 1D mesh x_0 < ... < x_n with degree p and boundary conditions: bc is one kind for
+    both ends, or a pair (left, right) of kinds; alpha the Robin coefficients of the ends."""
 
     x: np.ndarray  # breakpoints, length n+1
     p: int
-    bc: str
+    bc: object
+    alpha: tuple = (0.0, 0.0)
+
+    @property
+    def ends(self) -> tuple:
+        return (self.bc, self.bc) if isinstance(self.bc, str) else tuple(self.bc)
 
     @property
     def n(self) -> int:
@@ -63,7 +74,8 @@ class Basis1D:
 
     @property
     def nh(self) -> int:
-        return self.n - 1 if self.bc == DIRICHLET else self.n + 1
+        left, right = self.ends
+        return self.n - 1 + (left != DIRICHLET) + (right != DIRICHLET)
 
     @property
     def N(self) -> int:
@@ -75,9 +87,8 @@ class Basis1D:
 
     def hat_vertices(self) -> np.ndarray:
         """Vertex number of each retained hat, in index order."""
-        if self.bc == DIRICHLET:
-            return np.arange(1, self.n)
-        return np.arange(0, self.n + 1)
+        left, right = self.ends
+        return np.arange(0 if left != DIRICHLET else 1, self.n + 1 if right != DIRICHLET else self.n)
 
     def bubble_index(self, m, e):
         return self.nh + np.asarray(m) * self.n + np.asarray(e)
@@ -86,10 +97,13 @@ class Basis1D:
         return np.asarray(k) * self.n + np.asarray(e)
 
 
-def make_basis(n: int, p: int, a: float = 0.0, b: float = 1.0, bc: str = DIRICHLET,
-               breaks=None) -> Basis1D:
-    if bc not in (DIRICHLET, NEUMANN):
+def make_basis(n: int, p: int, a: float = 0.0, b: float = 1.0, bc=DIRICHLET,
+               breaks=None, alpha=(0.0, 0.0)) -> Basis1D:
+    ends = (bc, bc) if isinstance(bc, str) else tuple(bc)
+    if len(ends) != 2 or any(k not in (DIRICHLET, NEUMANN, ROBIN) for k in ends) or min(alpha) < 0:
         raise ValueError(bc)
+    if isinstance(bc, str) and bc == ROBIN:
+        raise ValueError("give Robin conditions per end")
     if p < 1 or n < 1:
         raise ValueError("need n >= 1 and p >= 1")
     if breaks is None:
@@ -98,7 +112,8 @@ def make_basis(n: int, p: int, a: float = 0.0, b: float = 1.0, bc: str = DIRICHL
         x = np.asarray(breaks, dtype=np.float64)
         if len(x) != n + 1 or np.any(np.diff(x) <= 0):
             raise ValueError("breaks must be n+1 increasing points")
-    return Basis1D(x=x, p=p, bc=bc)
+    alpha = tuple(float(alpha[i]) if ends[i] == ROBIN else 0.0 for i in range(2))
+    return Basis1D(x=x, p=p, bc=bc if isinstance(bc, str) else ends, alpha=alpha)
 
 
 # --------------------------------------------------------------------------
@@ -166,7 +181,7 @@ def legendre_mass(B: Basis1D) -> sp.dia_matrix:
 
 
 def restriction(B: Basis1D) -> sp.csr_matrix:
-    """P_D (Sec. 2.3): keeps every column of C except, for Dirichlet, the end hats."""
+    """P_D (Sec. 2.3): keeps every column of C except the hats of Dirichlet ends."""
     n, p = B.n, B.p
     ncols_full = (n + 1) + n * (p - 1)
     keep = list(B.hat_vertices()) + list(range(n + 1, ncols_full))
@@ -194,12 +209,23 @@ def assemble(B: Basis1D) -> Operators1D:
     PD = restriction(B)
     RY = (R @ PD).tocsr()
     DY = (D @ PD).tocsr()
-    K = (DY.T @ MP @ DY).tocsr()
+    K = (DY.T @ MP @ DY + robin_term(B)).tocsr()
     M = (RY.T @ MP @ RY).tocsr()
     T = (RY.T @ MP).tocsr()
     for A in (K, M, T):
         A.eliminate_zeros()
     return Operators1D(basis=B, K=K, M=M, T=T)
+
+
+def robin_term(B: Basis1D) -> sp.csr_matrix:
+    """alpha_l v(a) u(a) + alpha_r v(b) u(b) (Sec. 3.3's boundary term): the basis functions
+    evaluated at the two ends (eval_matrix), weighted by the Robin coefficients."""
+    out = sp.csr_matrix((B.N, B.N))
+    for side, xe in ((0, B.x[0]), (1, B.x[-1])):
+        if B.alpha[side] != 0.0:
+            e = eval_matrix(B, np.array([xe]))
+            out = out + B.alpha[side] * sp.csr_matrix(e.T @ e)
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -246,6 +272,10 @@ def assemble_quadrature(B: Basis1D, extra_points: int = 4) -> Operators1D:
                 K[i, j] += jac * np.sum(w * di * dj)
             for k in range(p + 1):
                 T[i, int(B.leg_index(k, e))] += jac * np.sum(w * vi * ss.eval_legendre(k, t))
+    # Robin ends: only the end vertex's hat is nonzero there, with value 1
+    for side, v in ((0, 0), (1, n)):
+        if B.alpha[side] != 0.0 and v in hat_pos:
+            K[hat_pos[v], hat_pos[v]] += B.alpha[side]
     return Operators1D(basis=B, K=sp.csr_matrix(K), M=sp.csr_matrix(M), T=sp.csr_matrix(T))
 
 
