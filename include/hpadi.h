@@ -55,7 +55,7 @@ enum {
     HPADI_ENOMEM = -7      /* device or host allocation failed */
 };
 
-enum { HPADI_DIRICHLET = 0, HPADI_NEUMANN = 1 };
+enum { HPADI_DIRICHLET = 0, HPADI_NEUMANN = 1, HPADI_ROBIN = 2 };
 enum { HPADI_FP64 = 0, HPADI_MIXED = 1 };
 
 typedef struct hpadi_op1d_s* hpadi_op1d;
@@ -98,6 +98,16 @@ typedef struct {
  * bc: HPADI_DIRICHLET or HPADI_NEUMANN.  Host-only; EINVAL on bad sizes. */
 int hpadi_op1d_create(int n, int p, double a, double b, const double* breaks, int bc,
                       hpadi_op1d* out);
+/* The same with a condition per end (Sec. 3.3, general boundary conditions): bc_left and
+ * bc_right are HPADI_DIRICHLET (the end's hat is dropped), HPADI_NEUMANN (kept) or
+ * HPADI_ROBIN: alpha u + du/dn = 0 at that end, the hat kept and alpha v(x) u(x) of the
+ * variational form added to K (alpha >= 0; alpha = 0 is Neumann).  Mixed conditions choose a
+ * different kind per end.  Inhomogeneous Robin data g enters the right-hand side as
+ * g v(x) at the end, i.e. g added to the end hat's entry of each column (row) of G.
+ * The hats kept are those of vertices first..last, first = 0 unless the left end is
+ * Dirichlet (then 1), last = n unless the right end is Dirichlet (then n - 1). */
+int hpadi_op1d_create_ex(int n, int p, double a, double b, const double* breaks, int bc_left, int bc_right,
+                         double alpha_left, double alpha_right, hpadi_op1d* out);
 /* N (basis size) and Nleg = (p+1) n (Legendre coefficients per dimension). */
 int hpadi_op1d_dims(hpadi_op1d op, int* N, int* Nleg);
 /* Dense row-major host copies: K and M are N x N, T = R^T M_P is N x Nleg
@@ -108,9 +118,12 @@ void hpadi_op1d_destroy(hpadi_op1d op);
 /* ---- Precomputation of Alg. 2 (host) ---------------------------------- */
 
 /* [lo, hi] containing the generalised eigenvalues of (K + omega2/2 M, M)
- * (Alg. 2 precomputation; Sec. 5.2 lemma "Spectrum").  Lower end in closed
- * form (pi^2/l^2 + omega2/2 Dirichlet, omega2/2 Neumann), upper end from a
- * Lanczos iteration with a 1% margin.  ESINGULAR for Neumann with omega2 <= 0. */
+ * (Alg. 2 precomputation; Sec. 5.2 lemma "Spectrum").  Lower end: the smallest
+ * eigenvalue of -u'' on the interval with the operator's end conditions (pi^2/l^2 for
+ * Dirichlet at both ends, 0 for Neumann at both, (pi/(2l))^2 for one of each, a
+ * bisection root for Robin ends), plus omega2/2: a Galerkin eigenvalue is never below
+ * it.  Upper end from a Lanczos iteration with a 1% margin.  ESINGULAR for Neumann at
+ * both ends with omega2 <= 0. */
 int hpadi_interval(hpadi_op1d op, double omega2, double out[2]);
 
 /* Iteration count J = ceil(log(16 gamma) log(4/tol)/pi^2) and Zolotarev shifts
@@ -138,6 +151,17 @@ int hpadi_plan_create(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int
 int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, int precision,
                          const double* interval, void* hip_stream, const hpadi_options* opts,
                          hpadi_plan* out);
+/* Alg. 2 for A U C - D U B = F with general operators along each axis:
+ * A = coef[0] K_x + coef[1] M_x, D = M_x, C = M_y, B = -(coef[2] K_y + coef[3] M_y), i.e.
+ * A_x U M_y + M_x U A_y = G with A_x, A_y any positive definite combinations of the
+ * stiffness and mass matrices (anisotropic diffusion coef[0] u_xx + coef[2] u_yy, unequal
+ * screening).  hpadi_plan_create_ex is the case {1, omega2/2, 1, omega2/2}; hpadi_load,
+ * hpadi_solve and hpadi_apply work on the general operator.  EINVAL unless coef[0] > 0 and
+ * coef[2] > 0; ESINGULAR for a negative coef[1] or coef[3], or a zero one on an axis with
+ * Neumann conditions at both ends.  Other arguments as hpadi_plan_create_ex. */
+int hpadi_plan_create_general(hpadi_op1d x, hpadi_op1d y, const double coef[4], double tol, int precision,
+                              const double* interval, void* hip_stream, const hpadi_options* opts,
+                              hpadi_plan* out);
 /* J and (when non-NULL) the J shifts p, q and the interval of the plan's ADI
  * family (the inner family in MIXED mode). */
 int hpadi_plan_info(hpadi_plan plan, int* J, double* p, double* q, double interval[4]);

@@ -54,6 +54,9 @@ SparseOp build_op(const hpadi_op1d_s& o, double kap, double sig) {
         if (v == 0.0) return;
         rows[i].push_back({j, v});
     };
+    // Robin ends (Sec. 3.3): alpha v(x) u(x) at the end adds alpha to its hat's diagonal
+    for (int v : {0, o.n})
+        if (o.vertex_is_hat(v)) add(o.hat_of_vertex(v), o.hat_of_vertex(v), kap * o.robin(v));
     // hat-hat
     for (int e = 0; e < o.n; ++e) {
         const double d = o.delta[e];
@@ -409,15 +412,37 @@ int compute_shifts(const double iv[4], double tol, int J_in, int* Jout, std::vec
     return HPADI_OK;
 }
 
-int interval_of(const hpadi_op1d_s& o, double omega2, double out[2]) {
-    if (o.bc == HPADI_NEUMANN && !(omega2 > 0.0)) return HPADI_ESINGULAR;
-    if (omega2 < 0.0) return HPADI_ESINGULAR;
+// Smallest eigenvalue of -u'' = lambda u on [x_0, x_n] with the operator's end conditions
+// (a Galerkin eigenvalue is never below it).  With u = sin(k x + phi_l), an end condition
+// alpha u + du/dn = 0 fixes its phase by tan(phi) = k / alpha (Dirichlet 0, Neumann pi/2),
+// and k l + phi_l + phi_r = pi closes the interval; both phases grow with k, so the
+// smallest root on (0, pi / l] is found by bisection.
+double continuous_lowest(const hpadi_op1d_s& o) {
     const double ell = o.x[o.n] - o.x[0];
-    const double lo = (o.bc == HPADI_DIRICHLET) ? kPi * kPi / (ell * ell) + omega2 / 2.0 : omega2 / 2.0;
+    auto phase = [&](int end, double k) {
+        return o.kind[end] == HPADI_DIRICHLET ? 0.0 : std::atan2(k, o.alpha[end]);
+    };
+    auto f = [&](double k) { return k * ell + phase(0, k) + phase(1, k) - kPi; };
+    if (f(0.0) >= 0.0) return 0.0;  // Neumann at both ends
+    double lo = 0.0, hi = kPi / ell;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (f(mid) < 0.0) lo = mid;
+        else hi = mid;
+    }
+    return lo * lo;
+}
+
+// [lo, hi] containing the generalised eigenvalues of (kap K + sig M, M).
+int interval_of(const hpadi_op1d_s& o, double kap, double sig, double out[2]) {
+    if (!(kap > 0.0) || !std::isfinite(kap) || !std::isfinite(sig)) return HPADI_EINVAL;
+    if (sig < 0.0 || (o.k_singular() && !(sig > 0.0))) return HPADI_ESINGULAR;
+    const double lo = kap * continuous_lowest(o) + sig;
+    if (!(lo > 0.0)) return HPADI_ESINGULAR;
     if (o.N == 0) return HPADI_EINVAL;
     const double dmin = *std::min_element(o.delta.begin(), o.delta.end());
     const double dmax = *std::max_element(o.delta.begin(), o.delta.end());
-    if (o.n >= 16 && dmax - dmin <= 1e-12 * dmax) {
+    if (o.n >= 16 && dmax - dmin <= 1e-12 * dmax && o.alpha[0] == 0.0 && o.alpha[1] == 0.0) {
         // Upper end from the elements: x^T K x = sum_e x_e^T K_e x_e and likewise for M, so the
         // largest eigenvalue of (K, M) is at most the largest element-level one (a Dirichlet
         // constraint only lowers it).  An element of width delta has the pair (K_1/delta,
@@ -428,7 +453,8 @@ int interval_of(const hpadi_op1d_s& o, double omega2, double out[2]) {
         hpadi_op1d_s u;
         u.n = 1;
         u.p = o.p;
-        u.bc = HPADI_NEUMANN;
+        u.bc = 3;
+        u.kind[0] = u.kind[1] = HPADI_NEUMANN;
         u.x = {0.0, 1.0};
         u.delta = {1.0};
         u.nh = 2;
@@ -441,10 +467,10 @@ int interval_of(const hpadi_op1d_s& o, double omega2, double out[2]) {
         double lk = 0.0;
         if (!lanczos_lmax(u, K1, M1, M1f, &lk)) return HPADI_EINVAL;
         out[0] = lo;
-        out[1] = std::max((lk / (dmin * dmin) + omega2 / 2.0) * (1.0 + 1e-6), lo * 1.0000001);
+        out[1] = std::max((kap * lk / (dmin * dmin) + sig) * (1.0 + 1e-6), lo * 1.0000001);
         return HPADI_OK;
     }
-    SparseOp A = build_op(o, 1.0, omega2 / 2.0);
+    SparseOp A = build_op(o, kap, sig);
     SparseOp M = build_op(o, 0.0, 1.0);
     HostFactor Mf;
     if (!host_factor(o, M, Mf)) return HPADI_ENOTSPD;
@@ -494,6 +520,8 @@ int make_dim(DimHost& D, const hpadi_op1d_s& o) {
     D.dev.N = N;
     D.dev.Nleg = o.Nleg;
     D.dev.bc = o.bc;
+    D.dev.rob0 = (o.bc & 1) ? o.alpha[0] : 0.0;
+    D.dev.rob1 = (o.bc & 2) ? o.alpha[1] : 0.0;
     D.dev.delta = D.buf;
     D.dev.invdelta = D.buf + n;
     D.dev.mdiag = D.buf + 2 * n;
@@ -515,7 +543,8 @@ void free_dim(DimHost& D) {
 }
 
 bool same_op(const hpadi_op1d_s& a, const hpadi_op1d_s& b) {
-    return a.n == b.n && a.p == b.p && a.bc == b.bc && a.x == b.x;
+    return a.n == b.n && a.p == b.p && a.bc == b.bc && a.x == b.x && a.alpha[0] == b.alpha[0] &&
+           a.alpha[1] == b.alpha[1];
 }
 
 int factor_family(DimHost& D, const std::vector<double>& kap, const std::vector<double>& sig, FactorLayout& fl,
@@ -668,8 +697,8 @@ hpadi::SweepArgs adi_row_args(const hpadi_plan_s* P, const ShiftFamily& F, int j
     r.lg = P->lint;
     r.out = P->Wk;
     r.lout = P->lint;
-    r.kappa = 1.0;
-    r.tau = P->omega2 / 2.0 + F.Q[j];
+    r.kappa = P->ky;
+    r.tau = P->sy + F.Q[j];
     return r;
 }
 hpadi::SweepArgs adi_col_args(const hpadi_plan_s* P, const ShiftFamily& F, int j) {
@@ -680,8 +709,8 @@ hpadi::SweepArgs adi_col_args(const hpadi_plan_s* P, const ShiftFamily& F, int j
     c.lg = P->lint;
     c.out = P->Wk;
     c.lout = P->lint;
-    c.kappa = 1.0;
-    c.tau = j + 1 == F.J ? 0.0 : P->omega2 / 2.0 - F.P[j + 1];
+    c.kappa = P->kx;
+    c.tau = j + 1 == F.J ? 0.0 : P->sx - F.P[j + 1];
     return c;
 }
 // Arguments of the final mass solve U (+)= L^{-1} w.
@@ -763,8 +792,8 @@ int row_products(hpadi_plan_s* P, const double* U, long ldu) {
     a.out2 = P->T2;
     a.o2_sl = P->ldw;
     a.o2_sp = 1;
-    a.k2 = 1.0;
-    a.t2 = P->omega2 / 2.0;
+    a.k2 = P->ky;
+    a.t2 = P->sy;
     a.nlines = P->dx.op.N;
     return hpadi::launch_op_apply(P->dy.dev, a, false, P->stream) == hipSuccess ? HPADI_OK : HPADI_EHIP;
 }
@@ -791,8 +820,8 @@ int residual_into_r64(hpadi_plan_s* P, const double* G, long ldg, const double* 
     r.t_ld = P->ldw;
     r.r64 = P->R64;
     r.r64_ld = P->ldw;
-    r.ax_k = 1.0;
-    r.ax_t = P->omega2 / 2.0;
+    r.ax_k = P->kx;
+    r.ax_t = P->sx;
     r.alpha = 1.0;
     r.beta = -1.0;
     r.ncols = P->dy.op.N;
@@ -977,14 +1006,33 @@ const char* hpadi_strerror(int st) {
 }
 
 int hpadi_op1d_create(int n, int p, double a, double b, const double* breaks, int bc, hpadi_op1d* out) {
+    if (bc != HPADI_DIRICHLET && bc != HPADI_NEUMANN) {
+        if (out) *out = nullptr;
+        return HPADI_EINVAL;
+    }
+    return hpadi_op1d_create_ex(n, p, a, b, breaks, bc, bc, 0.0, 0.0, out);
+}
+
+int hpadi_op1d_create_ex(int n, int p, double a, double b, const double* breaks, int bc_left, int bc_right,
+                         double alpha_left, double alpha_right, hpadi_op1d* out) {
     if (!out) return HPADI_EINVAL;
     *out = nullptr;
-    if (n < 1 || p < 1 || n > 1000000 || p > 129 || (bc != HPADI_DIRICHLET && bc != HPADI_NEUMANN)) return HPADI_EINVAL;
+    const int kinds[2] = {bc_left, bc_right};
+    const double alphas[2] = {alpha_left, alpha_right};
+    for (int i = 0; i < 2; ++i) {
+        if (kinds[i] != HPADI_DIRICHLET && kinds[i] != HPADI_NEUMANN && kinds[i] != HPADI_ROBIN) return HPADI_EINVAL;
+        if (kinds[i] == HPADI_ROBIN && !(alphas[i] >= 0.0 && std::isfinite(alphas[i]))) return HPADI_EINVAL;
+    }
+    if (n < 1 || p < 1 || n > 1000000 || p > 129) return HPADI_EINVAL;
     hpadi_op1d_s* o = new (std::nothrow) hpadi_op1d_s;
     if (!o) return HPADI_ENOMEM;
     o->n = n;
     o->p = p;
-    o->bc = bc;
+    o->bc = (kinds[0] != HPADI_DIRICHLET ? 1 : 0) | (kinds[1] != HPADI_DIRICHLET ? 2 : 0);
+    for (int i = 0; i < 2; ++i) {
+        o->kind[i] = kinds[i];
+        o->alpha[i] = kinds[i] == HPADI_ROBIN ? alphas[i] : 0.0;
+    }
     o->x.resize(n + 1);
     if (breaks) {
         for (int i = 0; i <= n; ++i) o->x[i] = breaks[i];
@@ -998,7 +1046,7 @@ int hpadi_op1d_create(int n, int p, double a, double b, const double* breaks, in
         o->delta[e] = o->x[e + 1] - o->x[e];
         if (!(o->delta[e] > 0.0) || !std::isfinite(o->delta[e])) { delete o; return HPADI_EINVAL; }
     }
-    o->nh = bc == HPADI_DIRICHLET ? n - 1 : n + 1;
+    o->nh = n - 1 + (o->bc & 1) + ((o->bc >> 1) & 1);
     o->N = o->nh + n * (p - 1);
     o->Nleg = (p + 1) * n;
     if (o->N < 1) { delete o; return HPADI_EINVAL; }
@@ -1051,7 +1099,7 @@ void hpadi_op1d_destroy(hpadi_op1d op) { delete op; }
 
 int hpadi_interval(hpadi_op1d op, double omega2, double out[2]) {
     if (!op || !out) return HPADI_EINVAL;
-    return interval_of(*op, omega2, out);
+    return interval_of(*op, 1.0, omega2 / 2.0, out);
 }
 
 int hpadi_shifts(const double iv[4], double tol, int J_in, int* J, double* p, double* q, int maxJ) {
@@ -1079,23 +1127,22 @@ int build_family(hpadi_plan_s* P, const hpadi_op1d_s& x, const hpadi_op1d_s& y, 
     if ((rc = compute_shifts(P->interval, eps, 0, &F.J, F.P, F.Q)) != HPADI_OK) return rc;
     const int J = F.J;
     if (dmalloc(&F.status, 2 * J + 2) != hipSuccess) return HPADI_ENOMEM;
-    const double half = P->omega2 / 2.0;
-    // y family: K_y + (w/2 + p_j) M_y for j = 1..J, then M_y
-    std::vector<double> ky(J + 1, 1.0), sy(J + 1);
-    for (int j = 0; j < J; ++j) sy[j] = half + F.P[j];
+    // y family: ky K_y + (sy + p_j) M_y for j = 1..J, then M_y
+    std::vector<double> ky(J + 1, P->ky), sy(J + 1);
+    for (int j = 0; j < J; ++j) sy[j] = P->sy + F.P[j];
     ky[J] = 0.0;
     sy[J] = 1.0;
     if ((rc = factor_family(P->dy, ky, sy, P->fly, &F.facy64, F.status, P->stream)) != HPADI_OK) return rc;
-    // x family: K_x + (w/2 - q_j) M_x, then M_x; shared with y when operators and shifts coincide
-    bool shared = same_op(x, y);
+    // x family: kx K_x + (sx - q_j) M_x, then M_x; shared with y when operators and shifts coincide
+    bool shared = same_op(x, y) && P->kx == P->ky && P->sx == P->sy;
     for (int j = 0; j < J && shared; ++j) shared = (-F.Q[j] == F.P[j]);
     F.shared = shared;
     if (shared) {
         F.facx64 = F.facy64;
         P->flx = P->fly;
     } else {
-        std::vector<double> kx(J + 1, 1.0), sx(J + 1);
-        for (int j = 0; j < J; ++j) sx[j] = half - F.Q[j];
+        std::vector<double> kx(J + 1, P->kx), sx(J + 1);
+        for (int j = 0; j < J; ++j) sx[j] = P->sx - F.Q[j];
         kx[J] = 0.0;
         sx[J] = 1.0;
         if ((rc = factor_family(P->dx, kx, sx, P->flx, &F.facx64, F.status + J + 1, P->stream)) != HPADI_OK) return rc;
@@ -1113,14 +1160,14 @@ int build_family(hpadi_plan_s* P, const hpadi_op1d_s& x, const hpadi_op1d_s& y, 
     // folded per-pass records: row pass j (S_y(w/2 + p_j), product tau = w/2 + q_j) and
     // column pass j (S_x(w/2 - q_j), product tau = w/2 - p_{j+1}; none after the last)
     auto ptables = [&](DimHost& D, double* fac, const FactorLayout& fl, const std::vector<double>& tau,
-                       double** out) -> int {
+                       double kappa, double** out) -> int {
         if (!D.uniform || D.op.p < 2) return HPADI_OK;
         if (dmalloc(out, (size_t)J * D.op.p * 16) != hipSuccess) return HPADI_ENOMEM;
         double* td = nullptr;
         if (dmalloc(&td, J) != hipSuccess) return HPADI_ENOMEM;
         int r = HPADI_OK;
         if (hipMemcpyAsync(td, tau.data(), J * sizeof(double), hipMemcpyHostToDevice, P->stream) != hipSuccess ||
-            hpadi::launch_pass_tables(D.dev, J, fac, fl.stride, fac + (size_t)J * fl.stride, fl, td, 1.0, *out,
+            hpadi::launch_pass_tables(D.dev, J, fac, fl.stride, fac + (size_t)J * fl.stride, fl, td, kappa, *out,
                                       P->stream) != hipSuccess ||
             hipStreamSynchronize(P->stream) != hipSuccess)
             r = HPADI_EHIP;
@@ -1129,11 +1176,11 @@ int build_family(hpadi_plan_s* P, const hpadi_op1d_s& x, const hpadi_op1d_s& y, 
     };
     std::vector<double> tr(J), tc(J);
     for (int j = 0; j < J; ++j) {
-        tr[j] = half + F.Q[j];
-        tc[j] = j + 1 < J ? half - F.P[j + 1] : 0.0;
+        tr[j] = P->sy + F.Q[j];
+        tc[j] = j + 1 < J ? P->sx - F.P[j + 1] : 0.0;
     }
-    if ((rc = ptables(P->dy, F.facy64, P->fly, tr, &F.ptaby)) != HPADI_OK) return rc;
-    return ptables(P->dx, F.facx64, P->flx, tc, &F.ptabx);
+    if ((rc = ptables(P->dy, F.facy64, P->fly, tr, P->ky, &F.ptaby)) != HPADI_OK) return rc;
+    return ptables(P->dx, F.facx64, P->flx, tc, P->kx, &F.ptabx);
 }
 
 // The shift family for an FP64 refinement round that follows one whose error bound was
@@ -1174,10 +1221,27 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
                          const double* interval, void* hip_stream, const hpadi_options* opts, hpadi_plan* out) {
     if (!out) return HPADI_EINVAL;
     *out = nullptr;
-    if (!x || !y || !(tol > 0.0 && tol < 1.0) || !std::isfinite(omega2) ||
-        (precision != HPADI_FP64 && precision != HPADI_MIXED))
+    if (!std::isfinite(omega2)) return HPADI_EINVAL;
+    if (omega2 < 0.0) return HPADI_ESINGULAR;
+    const double coef[4] = {1.0, omega2 / 2.0, 1.0, omega2 / 2.0};
+    const int rc = hpadi_plan_create_general(x, y, coef, tol, precision, interval, hip_stream, opts, out);
+    if (rc == HPADI_OK) (*out)->omega2 = omega2;
+    return rc;
+}
+
+int hpadi_plan_create_general(hpadi_op1d x, hpadi_op1d y, const double coef[4], double tol, int precision,
+                              const double* interval, void* hip_stream, const hpadi_options* opts,
+                              hpadi_plan* out) {
+    if (!out) return HPADI_EINVAL;
+    *out = nullptr;
+    if (!x || !y || !coef || !(tol > 0.0 && tol < 1.0) || (precision != HPADI_FP64 && precision != HPADI_MIXED))
         return HPADI_EINVAL;
-    if (omega2 < 0.0 || ((x->bc == HPADI_NEUMANN || y->bc == HPADI_NEUMANN) && !(omega2 > 0.0)))
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(coef[i])) return HPADI_EINVAL;
+    if (!(coef[0] > 0.0) || !(coef[2] > 0.0)) return HPADI_EINVAL;
+    // both axis operators must be positive definite: K is singular only with Neumann at both ends
+    if (coef[1] < 0.0 || coef[3] < 0.0 || (x->k_singular() && !(coef[1] > 0.0)) ||
+        (y->k_singular() && !(coef[3] > 0.0)))
         return HPADI_ESINGULAR;
     if (x->p / 2 > 64 || y->p / 2 > 64 || x->nh > kMaxHats || y->nh > kMaxHats) return HPADI_EINVAL;
     hpadi_plan_s* P = new (std::nothrow) hpadi_plan_s;
@@ -1186,7 +1250,11 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
     if (!(P->opt.inner_tol > 0.0)) P->opt.inner_tol = 3e-7;
     if (P->opt.fp32_rounds <= 0) P->opt.fp32_rounds = 1;
     if (P->opt.max_rounds <= 0) P->opt.max_rounds = 8;
-    P->omega2 = omega2;
+    P->kx = coef[0];
+    P->sx = coef[1];
+    P->ky = coef[2];
+    P->sy = coef[3];
+    P->omega2 = 2.0 * coef[1];  // the screened problem's omega^2 when sx = sy (Burgers, batch keys)
     P->tol = tol;
     P->precision = precision;
     P->stream = (hipStream_t)hip_stream;
@@ -1196,9 +1264,9 @@ int hpadi_plan_create_ex(hpadi_op1d x, hpadi_op1d y, double omega2, double tol, 
         for (int i = 0; i < 4; ++i) P->interval[i] = interval[i];
     } else {
         double ix[2], iy[2];
-        if ((rc = interval_of(*x, omega2, ix)) != HPADI_OK) { plan_free(P); return rc; }
-        if (same_op(*x, *y)) { iy[0] = ix[0]; iy[1] = ix[1]; }
-        else if ((rc = interval_of(*y, omega2, iy)) != HPADI_OK) { plan_free(P); return rc; }
+        if ((rc = interval_of(*x, P->kx, P->sx, ix)) != HPADI_OK) { plan_free(P); return rc; }
+        if (same_op(*x, *y) && P->kx == P->ky && P->sx == P->sy) { iy[0] = ix[0]; iy[1] = ix[1]; }
+        else if ((rc = interval_of(*y, P->ky, P->sy, iy)) != HPADI_OK) { plan_free(P); return rc; }
         P->interval[0] = ix[0];
         P->interval[1] = ix[1];
         P->interval[2] = -iy[1];
@@ -1340,8 +1408,8 @@ int hpadi_apply(hpadi_plan P, const double* U, int ldu, double* Y, int ldy) {
     r.t_ld = P->ldw;
     r.r64 = Y;
     r.r64_ld = ldy;
-    r.ax_k = 1.0;
-    r.ax_t = P->omega2 / 2.0;
+    r.ax_k = P->kx;
+    r.ax_t = P->sx;
     r.alpha = 0.0;
     r.beta = 1.0;
     r.ncols = P->dy.op.N;

@@ -9,14 +9,23 @@
 #include "internal.h"
 
 // 1D operator (Sec. 2.2-2.3, App. A): mesh, degree and boundary condition.
+// Boundary conditions per end (Sec. 3.3): Dirichlet drops the end's hat; Neumann keeps it;
+// Robin keeps it and adds alpha to its stiffness diagonal.
 struct hpadi_op1d_s {
-    int n, p, bc, nh, N, Nleg;
+    int n, p, bc, nh, N, Nleg;      // bc: hat mask (bit 0 vertex 0, bit 1 vertex n)
+    int kind[2] = {HPADI_DIRICHLET, HPADI_DIRICHLET};
+    double alpha[2] = {0.0, 0.0};   // Robin coefficients (0 unless Robin)
     std::vector<double> x, delta;
 
-    bool vertex_is_hat(int v) const { return bc == HPADI_DIRICHLET ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n); }
-    int hat_of_vertex(int v) const { return bc == HPADI_DIRICHLET ? v - 1 : v; }
-    int vertex_of_hat(int h) const { return bc == HPADI_DIRICHLET ? h + 1 : h; }
+    int first_hat_vertex() const { return (bc & 1) ? 0 : 1; }
+    bool vertex_is_hat(int v) const { return v >= first_hat_vertex() && v <= ((bc & 2) ? n : n - 1); }
+    int hat_of_vertex(int v) const { return v - first_hat_vertex(); }
+    int vertex_of_hat(int h) const { return h + first_hat_vertex(); }
     int bubble(int m, int e) const { return nh + m * n + e; }
+    // alpha of the end at vertex v (0 for interior vertices and non-Robin ends)
+    double robin(int v) const { return (v == 0 ? alpha[0] : 0.0) + (v == n ? alpha[1] : 0.0); }
+    // K has a null space (the constants) only with Neumann conditions at both ends
+    bool k_singular() const { return bc == 3 && alpha[0] == 0.0 && alpha[1] == 0.0; }
 };
 
 // One axis of a plan: the operator and its device-side description.
@@ -49,6 +58,9 @@ struct ShiftFamily {
 struct hpadi_plan_s {
     DimHost dx, dy;
     double omega2 = 0.0, tol = 0.0;
+    // A_x = kx K_x + sx M_x, A_y = ky K_y + sy M_y (kx = ky = 1, sx = sy = omega2 / 2 for the
+    // screened Poisson problem): Alg. 2 with A = A_x, D = M_x, C = M_y, B = -A_y
+    double kx = 1.0, sx = 0.0, ky = 1.0, sy = 0.0;
     int precision = HPADI_FP64;
     hpadi_options opt{};
     double interval[4] = {0, 0, 0, 0};

@@ -10,7 +10,10 @@ namespace hpadi {
 
 // Device view of one 1D discretisation (Sec. 2.2: mesh, degree, boundary condition).
 struct DimDev {
-    int n, p, nh, N, Nleg, bc;  // bc: 0 Dirichlet, 1 Neumann
+    int n, p, nh, N, Nleg, bc;  // bc: hat mask, bit 0 vertex 0 carries a hat, bit 1 vertex n
+                                // (0 Dirichlet at both ends, 3 Neumann or Robin at both)
+    double rob0, rob1;          // Robin coefficients of the ends (0 unless Robin): alpha v(x) u(x)
+                                // at that end adds alpha to the stiffness diagonal of its hat
     const double* delta;        // element widths, n
     const double* invdelta;     // 1 / delta, n
     const double* mdiag;        // diagonal of M (length N), weights of the error estimate

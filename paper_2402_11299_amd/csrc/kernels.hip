@@ -21,11 +21,16 @@ namespace hpadi {
 
 namespace {
 
+// bc is the hat mask: bit 0 set when vertex 0 carries a hat, bit 1 when vertex n does.
 __device__ __forceinline__ bool vertex_is_hat(int bc, int n, int v) {
-    return bc == 0 ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n);
+    return v >= ((bc & 1) ? 0 : 1) && v <= ((bc & 2) ? n : n - 1);
 }
-__device__ __forceinline__ int hat_of_vertex(int bc, int v) { return bc == 0 ? v - 1 : v; }
-__device__ __forceinline__ int vertex_of_hat(int bc, int h) { return bc == 0 ? h + 1 : h; }
+__device__ __forceinline__ int hat_of_vertex(int bc, int v) { return v - ((bc & 1) ? 0 : 1); }
+__device__ __forceinline__ int vertex_of_hat(int bc, int h) { return h + ((bc & 1) ? 0 : 1); }
+// Robin coefficient of the end at vertex v (0 elsewhere): Sec. 3.3's boundary term on K
+__device__ __forceinline__ double robin_at(const DimDev& d, int v) {
+    return (v == 0 ? d.rob0 : 0.0) + (v == d.n ? d.rob1 : 0.0);
+}
 
 // ---------------------------------------------------------------------------
 // Factorisation (Alg. 1) of S = kappa K + sigma M, FP64.
@@ -89,7 +94,7 @@ __global__ void __launch_bounds__(256) factor_kernel(DimDev d, const double* __r
         double dup = 0.0;
         for (int h = nh - 1; h >= 0; --h) {
             const int v = vertex_of_hat(d.bc, h);
-            double a = 0.0;
+            double a = kap * robin_at(d, v);
             if (v >= 1) {  // element v-1 lies left of v: v is its right vertex
                 const int e = v - 1;
                 a += kap * d.invdelta[e] + sig * d.delta[e] / 3.0;
@@ -147,6 +152,7 @@ __device__ __forceinline__ void gather_km(const DimDev& d, const double* x, long
     if (pos < nh) {
         const int h = pos, v = vertex_of_hat(d.bc, h);
         const double xh = x[(long)h * sp];
+        Kx += robin_at(d, v) * xh;
         if (v >= 1) {
             const int q = v - 1;
             const double dq = d.delta[q], idq = d.invdelta[q];
@@ -241,7 +247,7 @@ __device__ __forceinline__ void hat_taps(const DimDev& d, int h, Taps<7>& t) {
     const double dr = has_r ? d.delta[qr] : 0.0, ir = has_r ? d.invdelta[qr] : 0.0;
     const bool hl = has_l && vertex_is_hat(d.bc, n, v - 1), hr = has_r && vertex_is_hat(d.bc, n, v + 1);
     t.idx[0] = h;
-    t.kc[0] = il + ir;
+    t.kc[0] = il + ir + robin_at(d, v);
     t.mc[0] = (dl + dr) * (1.0 / 3.0);
     t.idx[1] = hl ? h - 1 : h;
     t.kc[1] = hl ? -il : 0.0;

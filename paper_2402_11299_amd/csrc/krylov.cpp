@@ -212,6 +212,8 @@ int hpadi_varcoef_create_ex(hpadi_op1d x, hpadi_op1d y, const double* a_dev, int
                             void* hip_stream, hpadi_varcoef* out) {
     if (!x || !y || !out) return HPADI_EINVAL;
     *out = nullptr;
+    // the Gauss-point form has no boundary term: Robin ends are not supported here
+    if (x->alpha[0] != 0.0 || x->alpha[1] != 0.0 || y->alpha[0] != 0.0 || y->alpha[1] != 0.0) return HPADI_EINVAL;
     const int qx = x->p + 2, qy = y->p + 2;
     const long rows = (long)x->n * qx, cols = (long)y->n * qy;
     if ((a_dev && lda < cols) || (c_dev && ldc < cols)) return HPADI_EINVAL;

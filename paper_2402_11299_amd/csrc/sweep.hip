@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
             for (int h = lane; h < nh; h += 64) {
                 const int v = voh(d.bc, h);
                 const double xh = A2[h];
-                double r = 0.0;
+                double r = kap * robin_at(d, v) * xh;
                 if (v >= 1) {
                     const int q = v - 1;
                     const double dq = d.delta[q], idq = d.invdelta[q];

@@ -8,9 +8,14 @@
 namespace hpadi {
 namespace sweep_detail {
 
-__device__ __forceinline__ bool vhat(int bc, int n, int v) { return bc == 0 ? (v >= 1 && v <= n - 1) : (v >= 0 && v <= n); }
-__device__ __forceinline__ int hov(int bc, int v) { return bc == 0 ? v - 1 : v; }
-__device__ __forceinline__ int voh(int bc, int h) { return bc == 0 ? h + 1 : h; }
+// bc is the hat mask of DimDev: bit 0 vertex 0 carries a hat, bit 1 vertex n.
+__device__ __forceinline__ bool vhat(int bc, int n, int v) { return v >= ((bc & 1) ? 0 : 1) && v <= ((bc & 2) ? n : n - 1); }
+__device__ __forceinline__ int hov(int bc, int v) { return v - ((bc & 1) ? 0 : 1); }
+__device__ __forceinline__ int voh(int bc, int h) { return h + ((bc & 1) ? 0 : 1); }
+// Robin coefficient of the end at vertex v (0 elsewhere), on the stiffness diagonal of its hat
+__device__ __forceinline__ double robin_at(const DimDev& d, int v) {
+    return (v == 0 ? d.rob0 : 0.0) + (v == d.n ? d.rob1 : 0.0);
+}
 
 __device__ __forceinline__ long addr(const Layout& L, int i, int j) {
     const int ii = i >= L.nhr ? i + L.offr : i;

@@ -307,7 +307,7 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             for (int h = lane; h < nh; h += 64) {
                 const int v = voh(d.bc, h);
                 const double xh = A2[h];
-                double r = 0.0;
+                double r = kap * robin_at(d, v) * xh;
                 if (v >= 1) {
                     const int q = v - 1;
                     const double dq = d.delta[q], idq = d.invdelta[q];

@@ -19,7 +19,7 @@ struct AxisMap {
     int n;    // elements
     int m;    // entries per element (AX_VALUES)
     int nh;   // hats (AX_Q)
-    int bc;   // 0 Dirichlet, 1 Neumann (AX_Q)
+    int bc;   // hat mask (AX_Q): bit 0 vertex 0 carries a hat, bit 1 vertex n
 };
 
 // out[line, o(e, i)] = s_e sum_l Mat[i][l] in[line, g(e, l)] along one axis of a

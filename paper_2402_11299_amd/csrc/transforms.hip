@@ -30,9 +30,9 @@ __device__ __forceinline__ int local_index(const AxisMap& a, int e, int l) {
     if (a.layout == AX_VALUES) return e * a.m + l;
     if (a.layout == AX_LEGENDRE) return l * a.n + e;
     if (l >= 2) return a.nh + (l - 2) * a.n + e;
-    const int v = e + l;  // vertex of the local hat
-    if (a.bc == 0) return (v >= 1 && v <= a.n - 1) ? v - 1 : -1;
-    return v;
+    const int v = e + l;  // vertex of the local hat; bc is the hat mask (bit 0 vertex 0, bit 1 vertex n)
+    const int first = (a.bc & 1) ? 0 : 1, last = (a.bc & 2) ? a.n : a.n - 1;
+    return (v >= first && v <= last) ? v - first : -1;
 }
 
 

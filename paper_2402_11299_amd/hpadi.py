@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libhpadi.so")
 
 HPADI_OK, HPADI_EINVAL, HPADI_ENOTSPD, HPADI_ESINGULAR = 0, -1, -2, -3
 HPADI_EINTERVAL, HPADI_ENOCONV, HPADI_EHIP, HPADI_ENOMEM = -4, -5, -6, -7
-HPADI_DIRICHLET, HPADI_NEUMANN = 0, 1
+HPADI_DIRICHLET, HPADI_NEUMANN, HPADI_ROBIN = 0, 1, 2
 HPADI_FP64, HPADI_MIXED = 0, 1
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
@@ -48,6 +48,9 @@ class hpadi_krylov_stats(ctypes.Structure):
 SIGNATURES = {
     "hpadi_op1d_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          _c_double_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_op1d_create_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                            _c_double_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)]),
     "hpadi_op1d_dims": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_int_p]),
     "hpadi_op1d_export": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p, _c_double_p]),
     "hpadi_op1d_destroy": (None, [ctypes.c_void_p]),
@@ -60,6 +63,9 @@ SIGNATURES = {
     "hpadi_plan_create_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_int, _c_double_p, ctypes.c_void_p,
                                             ctypes.POINTER(hpadi_options), ctypes.POINTER(ctypes.c_void_p)]),
+    "hpadi_plan_create_general": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_double,
+                                                 ctypes.c_int, _c_double_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.POINTER(ctypes.c_void_p)]),
     "hpadi_plan_info": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, _c_double_p, _c_double_p, _c_double_p]),
     "hpadi_plan_export_factor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_double_p,
                                                 ctypes.c_size_t]),
@@ -183,6 +189,19 @@ def hpadi_op1d_create(n, p, a=0.0, b=1.0, breaks=None, bc=HPADI_DIRICHLET):
     return h
 
 
+def hpadi_op1d_create_ex(n, p, a=0.0, b=1.0, breaks=None, bc_left=HPADI_DIRICHLET, bc_right=HPADI_DIRICHLET,
+                         alpha_left=0.0, alpha_right=0.0):
+    import numpy as np
+    h = ctypes.c_void_p()
+    br = None
+    if breaks is not None:
+        br = np.ascontiguousarray(breaks, dtype=np.float64)
+    check(lib().hpadi_op1d_create_ex(int(n), int(p), float(a), float(b), _dptr(br) if br is not None else None,
+                                     int(bc_left), int(bc_right), float(alpha_left), float(alpha_right),
+                                     ctypes.byref(h)), "hpadi_op1d_create_ex")
+    return h
+
+
 def hpadi_op1d_dims(op):
     N, L = ctypes.c_int(), ctypes.c_int()
     check(lib().hpadi_op1d_dims(op, ctypes.byref(N), ctypes.byref(L)), "hpadi_op1d_dims")
@@ -233,6 +252,16 @@ def hpadi_plan_create(x, y, omega2, tol, precision=HPADI_FP64, interval=None, st
         st = lib().hpadi_plan_create_ex(x, y, float(omega2), float(tol), int(precision), iv,
                                         _stream_handle(stream), ctypes.byref(options), ctypes.byref(h))
     check(st, "hpadi_plan_create")
+    return h
+
+
+def hpadi_plan_create_general(x, y, coef, tol, precision=HPADI_FP64, interval=None, stream=None, options=None):
+    h = ctypes.c_void_p()
+    cf = (ctypes.c_double * 4)(*[float(v) for v in coef])
+    iv = (ctypes.c_double * 4)(*[float(v) for v in interval]) if interval is not None else None
+    check(lib().hpadi_plan_create_general(x, y, cf, float(tol), int(precision), iv, _stream_handle(stream),
+                                          ctypes.byref(options) if options is not None else None,
+                                          ctypes.byref(h)), "hpadi_plan_create_general")
     return h
 
 
@@ -427,14 +456,23 @@ def hpadi_strerror(status):
 # Small object layer.
 # --------------------------------------------------------------------------
 
-class Op1D:
-    """A 1D discretisation handle (mesh, degree, BC)."""
+_BC_CODES = {"dirichlet": HPADI_DIRICHLET, "neumann": HPADI_NEUMANN, "robin": HPADI_ROBIN}
 
-    def __init__(self, n, p, a=0.0, b=1.0, bc="dirichlet", breaks=None):
+
+class Op1D:
+    """A 1D discretisation handle (mesh, degree, boundary conditions).  bc: one kind for both
+    ends ("dirichlet" or "neumann") or a pair (left, right) of "dirichlet", "neumann",
+    "robin"; alpha: the Robin coefficients of the two ends."""
+
+    def __init__(self, n, p, a=0.0, b=1.0, bc="dirichlet", breaks=None, alpha=(0.0, 0.0)):
         self.n, self.p, self.a, self.b = n, p, a, b
         self.bc = bc
-        code = HPADI_DIRICHLET if bc == "dirichlet" else HPADI_NEUMANN
-        self.handle = hpadi_op1d_create(n, p, a, b, breaks, code)
+        if isinstance(bc, str):
+            code = HPADI_DIRICHLET if bc == "dirichlet" else HPADI_NEUMANN
+            self.handle = hpadi_op1d_create(n, p, a, b, breaks, code)
+        else:
+            self.handle = hpadi_op1d_create_ex(n, p, a, b, breaks, _BC_CODES[bc[0]], _BC_CODES[bc[1]],
+                                               alpha[0], alpha[1])
         self.N, self.Nleg = hpadi_op1d_dims(self.handle)
 
     def close(self):
@@ -453,11 +491,16 @@ class Plan:
     """Factorised ADI plan on the GPU (Alg. 2 precomputation)."""
 
     def __init__(self, x: Op1D, y: Op1D, omega2, tol, precision="fp64", interval=None, stream=None,
-                 options=None):
+                 options=None, coef=None):
+        """coef = (kx, sx, ky, sy): the general operator (kx K_x + sx M_x) U M_y + M_x U (ky K_y + sy M_y)
+        (omega2 is then ignored); default the screened Poisson operator with omega2."""
         self.x, self.y = x, y
         self.precision = precision
         code = HPADI_FP64 if precision == "fp64" else HPADI_MIXED
-        self.handle = hpadi_plan_create(x.handle, y.handle, omega2, tol, code, interval, stream, options)
+        if coef is None:
+            self.handle = hpadi_plan_create(x.handle, y.handle, omega2, tol, code, interval, stream, options)
+        else:
+            self.handle = hpadi_plan_create_general(x.handle, y.handle, coef, tol, code, interval, stream, options)
         self.J, self.p, self.q, self.interval = hpadi_plan_info(self.handle)
 
     def load(self, F):

@@ -193,3 +193,53 @@ def test_host_transform_tables_match_oracle(hp, p):
     Ed = hp.hpadi_transform_export(p, 3)
     assert np.abs(E - ref_i @ R).max() <= 4 * m * 2.0 ** -53
     assert np.abs(Ed - ref_i @ D).max() <= 10 * m * 2.0 ** -53   # D on [-1, 1]: d/dt
+
+
+@pytest.mark.parametrize("bc,alpha,breaks", [
+    (("dirichlet", "neumann"), (0.0, 0.0), None),
+    (("neumann", "dirichlet"), (0.0, 0.0), [0.0, 0.1, 0.5, 1.0]),
+    (("robin", "robin"), (2.0, 0.5), None),
+    (("robin", "dirichlet"), (7.0, 0.0), [0.0, 0.3, 0.45, 1.0]),
+    (("neumann", "robin"), (0.0, 0.25), None),
+])
+def test_host_general_ends_match_oracle(hp, bc, alpha, breaks):
+    """Mixed and Robin ends (Sec. 3.3): the library's K, M, T against the oracle's, and the
+    spectral interval against the oracle's continuous lower end and dense spectrum."""
+    n, p = 3, 7
+    op = hp.Op1D(n, p, 0.0, 1.0, bc, breaks, alpha=alpha)
+    K, M, T = hp.hpadi_op1d_export(op.handle)
+    B = obasis.make_basis(n, p, 0.0, 1.0, bc, breaks, alpha=alpha)
+    ref = obasis.assemble(B)
+    assert op.N == B.N
+    assert np.abs(K - ref.K.toarray()).max() <= 1e-13 * np.abs(K).max()
+    assert np.abs(M - ref.M.toarray()).max() <= 1e-15
+    assert np.abs(T - ref.T.toarray()).max() <= 1e-15
+    for w2 in (0.0, 3.0):
+        lo, hi = hp.hpadi_interval(op.handle, w2)
+        assert lo == pytest.approx(ospectrum.lower_end(ref, w2), rel=1e-12)
+        lmin, lmax = ospectrum.extreme_eigenvalues(ref, w2)
+        assert lo <= lmin + 1e-14 * lmax and lmax <= hi <= 1.02 * lmax
+
+
+def test_host_general_api_rejects_bad_input(hp):
+    c = hp.ctypes
+    h = c.c_void_p()
+    L = hp.lib()
+    assert L.hpadi_op1d_create_ex(4, 8, 0.0, 1.0, None, 5, 0, 0.0, 0.0, c.byref(h)) == hp.HPADI_EINVAL
+    assert L.hpadi_op1d_create_ex(4, 8, 0.0, 1.0, None, hp.HPADI_ROBIN, 0, -1.0, 0.0, c.byref(h)) == hp.HPADI_EINVAL
+    assert L.hpadi_op1d_create(4, 8, 0.0, 1.0, None, hp.HPADI_ROBIN, c.byref(h)) == hp.HPADI_EINVAL
+    nn = hp.Op1D(4, 8, 0.0, 1.0, "neumann")
+    dd = hp.Op1D(4, 8)
+    rob = hp.Op1D(4, 8, 0.0, 1.0, ("robin", "neumann"), alpha=(1.0, 0.0))
+    def create(x, y, coef):
+        cf = (c.c_double * 4)(*coef)
+        return L.hpadi_plan_create_general(x.handle, y.handle, cf, 1e-8, 0, None, None, None, c.byref(h))
+    assert create(dd, dd, (0.0, 1.0, 1.0, 1.0)) == hp.HPADI_EINVAL       # kx must be positive
+    assert create(dd, dd, (1.0, -1.0, 1.0, 1.0)) == hp.HPADI_ESINGULAR   # negative screening
+    assert create(nn, dd, (1.0, 0.0, 1.0, 0.0)) == hp.HPADI_ESINGULAR    # Neumann at both ends, no screening
+    assert create(dd, nn, (1.0, 0.0, 1.0, 0.0)) == hp.HPADI_ESINGULAR
+    assert not h.value
+    # a Robin end makes K definite: no screening needed (checked here only up to argument
+    # validation; the plan itself needs a GPU)
+    lo, hi = hp.hpadi_interval(rob.handle, 0.0)
+    assert lo > 0.0
