@@ -629,6 +629,8 @@ def main():
                    "N": x.N, "n": cfgD.nx, "p": cfgD.px, "tol": cfgD.tol, "J_inner": pm.J,
                    "J_refine": st_mixed.J_refine, "rounds": st_mixed.rounds, "fp32_rounds": st_mixed.fp32_rounds,
                    "est_rel_err": st_mixed.est_rel_err,
+                   "phase_ms": {"fp32_rounds": st_mixed.t_ms[0], "fp64_rounds": st_mixed.t_ms[1],
+                                "residuals": st_mixed.t_ms[2]},
                    "rel_err_vs_oracle": err_headline,
                    "rel_err_vs_oracle_roundtrip": err_rt, "plan_ms": t_plan_mixed * 1e3,
                    "first_plan_ms": t_plan_cold * 1e3,

@@ -72,7 +72,10 @@ typedef struct {
     double res_rel;      /* last FP64 relative residual ||G - A U|| / ||G|| (mixed mode) */
     int fp32_rounds;     /* rounds run with FP32 sweeps (mixed mode) */
     int J_refine;        /* ADI iterations per FP64 refinement round (mixed mode; J for FP64 plans) */
-    double t_ms[3];      /* reserved */
+    double t_ms[3];      /* mixed mode: GPU time of the FP32 rounds, of the FP64 rounds (ADI sweeps,
+                            right-hand side and final mass solve) and of the FP64 residuals, in ms,
+                            from events on the plan's stream; 0 for FP64 plans (no synchronisation:
+                            use hpadi_plan_timing) */
 } hpadi_stats;
 
 /* Options for hpadi_plan_create_ex (zero-initialise, then set fields). */

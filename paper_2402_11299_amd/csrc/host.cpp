@@ -596,6 +596,7 @@ void plan_free(hpadi_plan_s* P) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
     }
+    for (hipEvent_t e : P->phase_ev) hipEventDestroy(e);
     free_dim(P->dx);
     free_dim(P->dy);
     delete P;
@@ -1448,6 +1449,14 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
         const int maxr = P->opt.fixed_rounds > 0 ? P->opt.fixed_rounds : P->opt.max_rounds;
         int k = 0, nfp32 = P->opt.fp32_rounds, k0 = 0;
         bool done = false;
+        // phase times (stats t_ms): three events per round, before it, after its ADI sweeps
+        // and after the residual that follows; read once the last round has been synchronised
+        while ((int)P->phase_ev.size() < 3 * maxr) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return HPADI_EHIP;
+            P->phase_ev.push_back(e);
+        }
+        std::vector<int> round_fp32, round_res;
         for (k = 1; k <= maxr; ++k) {
             // k0: rounds discarded by a restart in FP64 (an FP32 round that overflowed)
             const bool fp32 = k - k0 <= nfp32;
@@ -1460,10 +1469,15 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
             const double eps = F.eps;
             // round 1 starts from U = 0 (acc[4], the norm of U before the round, stays 0)
             const bool first = k == k0 + 1;
+            hipEvent_t* ev = P->phase_ev.data() + 3 * (k - 1);
+            if (hipEventRecord(ev[0], s) != hipSuccess) return HPADI_EHIP;
+            round_fp32.push_back(fp32 ? 1 : 0);
+            round_res.push_back(0);
             if (hpadi::launch_zero_f64(P->acc, first ? 5 : 1, 1, first ? 5 : 1, s) != hipSuccess) return HPADI_EHIP;
             if ((rc = transform_rhs(P, first ? G : P->R64, first ? ldg : P->ldw, ts)) != HPADI_OK) return rc;
             // the first round writes U, later rounds add their correction to it
             if ((rc = run_adi(P, F, ts, U, ldu, !first, true)) != HPADI_OK) return rc;
+            if (hipEventRecord(ev[1], s) != hipSuccess) return HPADI_EHIP;
             st.iters += F.J;
             if (fp32) st.fp32_rounds++;
             const bool decide = P->opt.fixed_rounds <= 0 && !fp32;
@@ -1496,8 +1510,17 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
             }
             // r = G - A U in FP64
             if ((rc = residual_into_r64(P, G, ldg, U, ldu)) != HPADI_OK) return rc;
+            if (hipEventRecord(ev[2], s) != hipSuccess) return HPADI_EHIP;
+            round_res.back() = 1;
         }
         if (k > maxr) k = maxr;
+        // every recorded event precedes the last synchronisation
+        for (size_t r = 0; r < round_fp32.size(); ++r) {
+            const hipEvent_t* ev = P->phase_ev.data() + 3 * r;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) st.t_ms[round_fp32[r] ? 0 : 1] += ms;
+            if (round_res[r] && hipEventElapsedTime(&ms, ev[1], ev[2]) == hipSuccess) st.t_ms[2] += ms;
+        }
         st.rounds = k;
         st.est_rel_err = est;
         if (P->opt.fixed_rounds <= 0 && !done) rc = HPADI_ENOCONV;

@@ -93,6 +93,7 @@ struct hpadi_plan_s {
     double* part = nullptr;       // per-block partial sums of the residual's norms
     double* acc_host = nullptr;   // pinned host copy
     // measurement
+    std::vector<hipEvent_t> phase_ev;  // per-round events of a mixed solve (stats t_ms)
     bool timing = false;
     struct Rec { hipEvent_t a, b; int kind; double bytes; };
     std::vector<Rec> recs;        // event pool; the first nrec are in use

@@ -135,9 +135,11 @@ def test_mixed_precision_reaches_tolerance(hp, torch, nx, px, ny, py, bc, w2):
     U, st = plan.solve(torch.from_numpy(G).cuda())
     Uref = oadi.solve_fdm(ox, oy, w2, G, refine=2)
     err = oadi.rel_l2_error(U.cpu().numpy(), Uref, ox, oy)
-    print("mixed rounds", st.rounds, "est", st.est_rel_err, "err", err, flush=True)
+    print("mixed rounds", st.rounds, "est", st.est_rel_err, "err", err, "phase ms", list(st.t_ms), flush=True)
     assert st.est_rel_err <= 1e-10 and err <= st.est_rel_err + ROUNDING_ALLOWANCE
     assert st.rounds >= 2
+    # phase times: FP32 rounds, FP64 rounds and residuals all ran
+    assert st.t_ms[0] > 0 and st.t_ms[1] > 0 and st.t_ms[2] > 0
     plan.close()
 
 
