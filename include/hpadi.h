@@ -233,9 +233,12 @@ void hpadi_plan_destroy(hpadi_plan plan);
  * launches of one step touch disjoint instances and are captured as parallel
  * branches over four streams (the origin and three of the batch's own, default
  * priority), joined before the next step.  Both rounds use one shift family (3e-6).
- * autotune != 0: for every distinct (n_x, p_x, n_y, p_y, bc) the lines per
- * workgroup (4 or 8) is chosen by timing both on the instance (this runs solves
- * and overwrites U[i]).  G[i], U[i]: FP64 device arrays N_x x N_y (ld ldg[i],
+ * autotune != 0: for every distinct (n_x, p_x, n_y, p_y, boundary conditions) the
+ * lines per workgroup (4 or 8) is chosen by timing both on the instance (this runs
+ * solves and overwrites U[i]).  When the environment variable HPADI_TUNE_CACHE names
+ * a file, choices found there for this GPU architecture are used without timing and
+ * new ones are appended (text, one line per key); an unreadable or unwritable file
+ * only disables the cache.  G[i], U[i]: FP64 device arrays N_x x N_y (ld ldg[i],
  * ldu[i]) bound to the graph: later solves read and write these same arrays.
  * nstreams: reserved, pass 0.  hip_stream: the stream the graph is launched on (a
  * hipStream_t, or NULL for a stream of the batch's own). */

@@ -7,6 +7,9 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
@@ -1530,6 +1533,29 @@ int hpadi_solve(hpadi_plan P, const double* G, int ldg, double* U, int ldu, hpad
     return rc;
 }
 
+namespace {
+// On-disk autotune results: one line per key, "arch n_x p_x n_y p_y mask_x mask_y lines".
+void load_tune_cache(const char* path, const std::string& arch, std::vector<std::pair<std::vector<int>, int>>& out) {
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char a[64];
+    int v[7];
+    while (std::fscanf(f, "%63s %d %d %d %d %d %d %d", a, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]) == 8)
+        if (arch == a && (v[6] == 4 || v[6] == 8)) out.push_back({{v[0], v[1], v[2], v[3], v[4], v[5]}, v[6]});
+    std::fclose(f);
+}
+void save_tune_cache(const char* path, const std::string& arch, const std::vector<std::pair<std::vector<int>, int>>& t,
+                     size_t from) {
+    std::FILE* f = std::fopen(path, "a");
+    if (!f) return;  // the cache is an optimisation: a read-only location is not an error
+    for (size_t i = from; i < t.size(); ++i) {
+        const std::vector<int>& k = t[i].first;
+        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", arch.c_str(), k[0], k[1], k[2], k[3], k[4], k[5], t[i].second);
+    }
+    std::fclose(f);
+}
+}  // namespace
+
 int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, const double* omega2, double tol,
                        const double* const* G, const int* ldg, double* const* U, const int* ldu, int autotune,
                        int nstreams, void* hip_stream, hpadi_batch* out) {
@@ -1555,9 +1581,22 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         B->own_origin = true;
     }
     (void)nstreams;
-    // autotuner: lines per workgroup (4 or 8) per distinct (n_x, p_x, n_y, p_y, bc), by timing
-    // one fixed-schedule solve of each candidate on the instance's own data
+    // autotuner: lines per workgroup (4 or 8) per distinct (n_x, p_x, n_y, p_y, hat masks), by
+    // timing one fixed-schedule solve of each candidate on the instance's own data; results
+    // persist in the file named by HPADI_TUNE_CACHE (if set), keyed by the GPU architecture
     std::vector<std::pair<std::vector<int>, int>> tuned;
+    const char* cache_path = std::getenv("HPADI_TUNE_CACHE");
+    std::string arch = "gpu";
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            arch = prop.gcnArchName;
+            arch = arch.substr(0, arch.find(':'));
+        }
+    }
+    if (autotune && cache_path) load_tune_cache(cache_path, arch, tuned);
+    const size_t ncached = tuned.size();
     B->plans.assign(count, nullptr);
     B->lw.assign(count, 4);
     B->G.assign(G, G + count);
@@ -1580,7 +1619,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
         return HPADI_OK;
     };
     for (int i = 0; i < count; ++i) {
-        const std::vector<int> key = {xs[i]->n, xs[i]->p, ys[i]->n, ys[i]->p, xs[i]->bc};
+        const std::vector<int> key = {xs[i]->n, xs[i]->p, ys[i]->n, ys[i]->p, xs[i]->bc, ys[i]->bc};
         int lw = 4;
         bool found = false;
         for (auto& kv : tuned)
@@ -1631,6 +1670,7 @@ int hpadi_batch_create(int count, const hpadi_op1d* xs, const hpadi_op1d* ys, co
             return rc;
         }
     }
+    if (autotune && cache_path && tuned.size() > ncached) save_tune_cache(cache_path, arch, tuned, ncached);
     // device table of accumulator pointers and their gathered copy
     std::vector<double*> accs(count);
     for (int i = 0; i < count; ++i) accs[i] = B->plans[i]->acc;

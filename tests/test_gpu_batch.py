@@ -134,3 +134,30 @@ def test_batch_512_every_instance_against_the_oracle(hp):
         checked += 1
     print(f"  bench right-hand sides: {checked} instances checked against the oracle", flush=True)
     batch.close()
+
+
+def test_batch_tune_cache(hp, tmp_path, monkeypatch):
+    """The on-disk autotune cache (HPADI_TUNE_CACHE): a choice written for this GPU's
+    architecture is used without timing (here 8 lines per workgroup for the Dirichlet key,
+    whatever the timing would pick), and a key the cache lacks is tuned and appended."""
+    import torch
+    path = tmp_path / "tune.txt"
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path.write_text(f"{arch} 8 16 8 16 0 0 8\nother 8 16 8 16 0 0 4\n")
+    monkeypatch.setenv("HPADI_TUNE_CACHE", str(path))
+    probs, Gs, Us = [], [], []
+    for k, (n, p, bc, w2) in enumerate([(8, 16, "dirichlet", 0.0), (4, 32, "neumann", 1.0)]):
+        x = hp.Op1D(n, p, 0.0, 1.0, bc)
+        G = torch.from_numpy(workloads.decaying_coefficients(n, p, n, p, bc, seed=70 + k)).cuda()
+        probs.append((x, x, w2))
+        Gs.append(G)
+        Us.append(torch.empty_like(G))
+    batch = hp.Batch(probs, 1e-10, Gs, Us, autotune=True)
+    st, _ = batch.solve()
+    assert all(s.status == hp.HPADI_OK for s in st)
+    assert batch.info(0)[0] == 8
+    lines = path.read_text().splitlines()
+    print("cache:", lines, flush=True)
+    assert len(lines) == 3 and lines[2].startswith(f"{arch} 4 32 4 32 3 3 ")
+    assert int(lines[2].split()[-1]) == batch.info(1)[0]
+    batch.close()
