@@ -131,6 +131,10 @@ struct TrAxis {
     double* inv = nullptr;
     double* ev = nullptr;
     double* dv = nullptr;
+    double* fwd_r = nullptr; // the same matrices row-major (tail rows of the passes)
+    double* inv_r = nullptr;
+    double* ev_r = nullptr;
+    double* dv_r = nullptr;
     double* two_over_delta = nullptr;  // 2 / delta_e
 };
 
@@ -159,10 +163,12 @@ struct hpadi_transform_s {
         std::vector<double> tod(op.n);
         for (int e = 0; e < op.n; ++e) tod[e] = 2.0 / op.delta[e];
         int rc;
-        if ((rc = upload(fragments(forward_matrix(a.p), a.m, a.m), &a.fwd)) ||
-            (rc = upload(fragments(inverse_matrix(a.p), a.m, a.m), &a.inv)) ||
-            (rc = upload(fragments(local_basis_matrix(a.p, false), a.m, a.m), &a.ev)) ||
-            (rc = upload(fragments(local_basis_matrix(a.p, true), a.m, a.m), &a.dv)) ||
+        const std::vector<double> F = forward_matrix(a.p), I = inverse_matrix(a.p);
+        const std::vector<double> E = local_basis_matrix(a.p, false), D = local_basis_matrix(a.p, true);
+        if ((rc = upload(fragments(F, a.m, a.m), &a.fwd)) || (rc = upload(fragments(I, a.m, a.m), &a.inv)) ||
+            (rc = upload(fragments(E, a.m, a.m), &a.ev)) || (rc = upload(fragments(D, a.m, a.m), &a.dv)) ||
+            (rc = upload(F, &a.fwd_r)) || (rc = upload(I, &a.inv_r)) || (rc = upload(E, &a.ev_r)) ||
+            (rc = upload(D, &a.dv_r)) ||
             (rc = upload(tod, &a.two_over_delta)))
             return rc;
         return HPADI_OK;
@@ -172,15 +178,22 @@ struct hpadi_transform_s {
 namespace {
 
 // A pass along x (rows) of the transform's x axis, or along y (columns) of its y axis.
-hpadi::ElemPass make_pass(const TrAxis& a, int lin, int lout, const double* tab, const double* in, long ldin,
-                          double* out, long ldout, int lines) {
+// tab_r: the same matrix row-major (its tail rows).
+hpadi::ElemPass make_pass(const TrAxis& a, int lin, int lout, const double* tab, const double* tab_r,
+                          const double* in, long ldin, double* out, long ldout, int lines) {
     hpadi::ElemPass e{};
     e.in = in; e.ldin = ldin; e.out = out; e.ldout = ldout;
     e.ain = axis_map(a, lin);
     e.aout = axis_map(a, lout);
     e.L = a.m;  // m points, p + 1 degrees, p + 1 local basis functions
     e.M = a.m;
-    e.nwaves = (a.m + 15) / 16;
+    // m = 16 k + r with k >= 4 and r <= 4 (m = 65, 129: r = 1): k matrix-core waves and r
+    // tail rows by vector FMAs; otherwise ceil(m / 16) waves
+    const int k = a.m / 16, r = a.m % 16;
+    const bool tail = k >= 4 && r > 0 && r <= 4;
+    e.nwaves = tail ? k : (a.m + 15) / 16;
+    e.tail = tail ? r : 0;
+    e.ttab = tail ? tab_r + (size_t)16 * k * a.m : nullptr;
     e.ksteps = (a.m + 3) / 4;
     e.tab = tab;
     e.lines = lines;
@@ -193,10 +206,10 @@ int forward(hpadi_transform_s* T, const double* V, long ldv, double* F, long ldf
     const TrAxis &X = T->ax[0], &Y = T->ax[1];
     const int nlx = X.n * X.m, nly = Y.n * Y.m;
     hipError_t e = hpadi::launch_elem_rows(
-        make_pass(X, hpadi::AX_VALUES, hpadi::AX_LEGENDRE, X.fwd, V, ldv, T->S, T->lds, nly), T->stream);
+        make_pass(X, hpadi::AX_VALUES, hpadi::AX_LEGENDRE, X.fwd, X.fwd_r, V, ldv, T->S, T->lds, nly), T->stream);
     if (e == hipSuccess)
         e = hpadi::launch_elem_cols(
-            make_pass(Y, hpadi::AX_VALUES, hpadi::AX_LEGENDRE, Y.fwd, T->S, T->lds, F, ldf, nlx), T->stream);
+            make_pass(Y, hpadi::AX_VALUES, hpadi::AX_LEGENDRE, Y.fwd, Y.fwd_r, T->S, T->lds, F, ldf, nlx), T->stream);
     return hip_status(e);
 }
 
@@ -204,17 +217,17 @@ int inverse(hpadi_transform_s* T, const double* F, long ldf, double* V, long ldv
     const TrAxis &X = T->ax[0], &Y = T->ax[1];
     const int nlx = X.n * X.m, nly = Y.n * Y.m;
     hipError_t e = hpadi::launch_elem_rows(
-        make_pass(X, hpadi::AX_LEGENDRE, hpadi::AX_VALUES, X.inv, F, ldf, T->S, T->lds, nly), T->stream);
+        make_pass(X, hpadi::AX_LEGENDRE, hpadi::AX_VALUES, X.inv, X.inv_r, F, ldf, T->S, T->lds, nly), T->stream);
     if (e == hipSuccess)
         e = hpadi::launch_elem_cols(
-            make_pass(Y, hpadi::AX_LEGENDRE, hpadi::AX_VALUES, Y.inv, T->S, T->lds, V, ldv, nlx), T->stream);
+            make_pass(Y, hpadi::AX_LEGENDRE, hpadi::AX_VALUES, Y.inv, Y.inv_r, T->S, T->lds, V, ldv, nlx), T->stream);
     return hip_status(e);
 }
 
 // Y-pass of the evaluation: S = U E_y^T (values along y), N_x rows.
 hipError_t eval_cols(hpadi_transform_s* T, const double* U, long ldu) {
     const TrAxis &X = T->ax[0], &Y = T->ax[1];
-    return hpadi::launch_elem_cols(make_pass(Y, hpadi::AX_Q, hpadi::AX_VALUES, Y.ev, U, ldu, T->S, T->lds, X.N),
+    return hpadi::launch_elem_cols(make_pass(Y, hpadi::AX_Q, hpadi::AX_VALUES, Y.ev, Y.ev_r, U, ldu, T->S, T->lds, X.N),
                                    T->stream);
 }
 
@@ -277,7 +290,7 @@ int hpadi_q_to_values(hpadi_transform T, int deriv_x, const double* U, int ldu, 
     if (ldu < Y.N || ldv < Y.n * Y.m) return HPADI_EINVAL;
     hipError_t e = eval_cols(T, U, ldu);
     if (e != hipSuccess) return HPADI_EHIP;
-    hpadi::ElemPass r = make_pass(X, hpadi::AX_Q, hpadi::AX_VALUES, deriv_x ? X.dv : X.ev, T->S, T->lds, V, ldv,
+    hpadi::ElemPass r = make_pass(X, hpadi::AX_Q, hpadi::AX_VALUES, deriv_x ? X.dv : X.ev, deriv_x ? X.dv_r : X.ev_r, T->S, T->lds, V, ldv,
                                   Y.n * Y.m);
     if (deriv_x) r.scale = X.two_over_delta;
     return hip_status(hpadi::launch_elem_rows(r, T->stream));
@@ -353,8 +366,9 @@ int hpadi_burgers_step(hpadi_burgers B, double* F, int ldf, int nsteps, hpadi_st
         // values of u and u_x at the grid and the explicit Euler step of the nonlinear part,
         // w = u - dt u u_x, fused into the x pass of the evaluation
         if (eval_cols(T, B->U, B->ldn) != hipSuccess) return HPADI_EHIP;
-        hpadi::ElemPass r = make_pass(X, hpadi::AX_Q, hpadi::AX_VALUES, X.ev, T->S, T->lds, B->W, T->lds, nly);
+        hpadi::ElemPass r = make_pass(X, hpadi::AX_Q, hpadi::AX_VALUES, X.ev, X.ev_r, T->S, T->lds, B->W, T->lds, nly);
         r.tab2 = X.dv;
+        if (r.tail) r.ttab2 = X.dv_r + (size_t)16 * r.nwaves * X.m;
         r.scale2 = X.two_over_delta;
         r.dt = B->dt;
         if (hpadi::launch_elem_rows(r, T->stream) != hipSuccess) return HPADI_EHIP;

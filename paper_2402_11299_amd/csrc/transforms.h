@@ -25,7 +25,7 @@ struct AxisMap {
 // out[line, o(e, i)] = s_e sum_l Mat[i][l] in[line, g(e, l)] along one axis of a
 // row-major array, for every element e and output i < M.  The matrix is stored as the A
 // operands of v_mfma_f64_16x16x4f64: tab[((w S + s) 64 + lane)] = Mat[16 w + lane % 16]
-// [4 s + lane / 16] (zero outside M x L), w < nwaves = ceil(M / 16), s < ksteps = ceil(L / 4).
+// [4 s + lane / 16] (zero outside M x L), w < ceil(M / 16), s < ksteps = ceil(L / 4).
 // A workgroup of nwaves waves stages the inputs of 64 lines in LDS (max(4 ksteps, 16 nwaves)
 // x 80 doubles, at most 160 KiB).  With tab2 set (Burgers epilogue, row passes only) a
 // second matrix scaled per element by scale2[e] gives w = tab2 . in, and the pass stores
@@ -35,7 +35,11 @@ struct ElemPass {
     double* out; long ldout;
     AxisMap ain, aout;
     int L, M;              // inputs and outputs per element
-    int nwaves, ksteps;    // ceil(M / 16), ceil(L / 4)
+    int nwaves, ksteps;    // matrix-core waves (16 output rows each) and ceil(L / 4)
+    int tail;              // output rows 16 nwaves .. M - 1 done by vector FMAs (0, or <= 4 with
+                           // nwaves >= 4)
+    const double* ttab;    // those rows of the matrix, row-major (tail x L)
+    const double* ttab2;   // the same of the second matrix (tab2 set)
     const double* tab;
     const double* tab2;    // or NULL
     const double* scale;   // per-element factor of tab (NULL = 1)

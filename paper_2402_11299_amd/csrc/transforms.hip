@@ -41,7 +41,7 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 constexpr int kLines = 64;     // lines per workgroup
 constexpr int kStride = 65;    // LDS row stride (doubles): odd, so that walking a tile column
                                // (consecutive l of one line) spreads over the banks
-constexpr int kBatch = 16;     // loads in flight per thread while staging
+constexpr int kBatch = 24;     // loads in flight per thread while staging (one batch covers a tile)
 constexpr int kMaxKsteps = 60; // L <= 240
 
 // Column passes: the 64 items of a workgroup are R rows x E consecutive elements.
@@ -153,6 +153,35 @@ __global__ void __launch_bounds__(1024) elem_pass_kernel(ElemPass a) {
             }
         }
     }
+    // ---- tail rows 16 nwaves .. M - 1 (at most 4, when M = 16 nwaves + tail): vector FMAs
+    // in the first four waves, wave w for lines 16 w .. 16 w + 15, each 16-lane group of
+    // it a quarter of the inputs, the quarters summed by cross-lane adds.  This keeps one
+    // wave per SIMD where a padded wave would add a fifth for a single output row.
+    const int T = a.tail, i0t = 16 * a.nwaves;
+    double tv[4] = {0.0, 0.0, 0.0, 0.0}, tv2[4] = {0.0, 0.0, 0.0, 0.0};
+    if (T > 0 && w < 4) {
+        const int line = 16 * w + jc;
+        for (int l = kr; l < L; l += 4) {
+            const double x = tile[l * kStride + line];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t < T) {
+                    tv[t] = fma(a.ttab[t * L + l], x, tv[t]);
+                    if (BURG) tv2[t] = fma(a.ttab2[t * L + l], x, tv2[t]);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            tv[t] += __shfl_xor(tv[t], 16, 64);
+            tv[t] += __shfl_xor(tv[t], 32, 64);
+            if (BURG) {
+                tv2[t] += __shfl_xor(tv2[t], 16, 64);
+                tv2[t] += __shfl_xor(tv2[t], 32, 64);
+            }
+        }
+    }
+    const bool tail_lane = T > 0 && w < 4 && kr == 0;  // stores the tail rows of line 16 w + jc
     // ---- results: output row i = 16 w + kr + 4 r, line 16 ct + jc
     if (ROWS) {
         const double sc = a.scale ? a.scale[e] : 1.0;
@@ -171,6 +200,13 @@ __global__ void __launch_bounds__(1024) elem_pass_kernel(ElemPass a) {
                 orow[j] = v;
             }
         }
+        if (tail_lane && c0 + 16 * w + jc < a.lines) {
+            for (int t = 0; t < T; ++t) {
+                double v = tv[t] * sc;
+                if (BURG) v = v - a.dt * (tv2[t] * s2) * v;
+                a.out[(long)local_index(a.aout, e, i0t + t) * a.ldout + c0 + 16 * w + jc] = v;
+            }
+        }
         return;
     }
     if (a.aout.layout != AX_VALUES) {
@@ -185,6 +221,15 @@ __global__ void __launch_bounds__(1024) elem_pass_kernel(ElemPass a) {
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * w + kr + 4 * r;
                 if (i < a.M) orow[local_index(a.aout, e0 + el, i)] = acc[ct][r] * sc;
+            }
+        }
+        if (tail_lane) {
+            const int j = 16 * w + jc;
+            const int rl = j / E, el = j - rl * E;
+            if (rl < rows && el < En) {
+                const double sc = a.scale ? a.scale[e0 + el] : 1.0;
+                double* orow = a.out + (long)(r0 + rl) * a.ldout;
+                for (int t = 0; t < T; ++t) orow[local_index(a.aout, e0 + el, i0t + t)] = tv[t] * sc;
             }
         }
         return;
@@ -202,6 +247,12 @@ __global__ void __launch_bounds__(1024) elem_pass_kernel(ElemPass a) {
             if (i < a.M) tile[i * kStride + j] = acc[ct][r] * sc;
         }
     }
+    if (tail_lane) {
+        const int j = 16 * w + jc;
+        const int rl = j / E, el = j - rl * E;
+        const double sc = (a.scale && rl < rows && el < En) ? a.scale[e0 + el] : 1.0;
+        for (int t = 0; t < T; ++t) tile[(i0t + t) * kStride + j] = tv[t] * sc;
+    }
     __syncthreads();
     const int M = a.M, seg = En * M;
     for (int idx = threadIdx.x; idx < rows * seg; idx += nt) {
@@ -211,8 +262,11 @@ __global__ void __launch_bounds__(1024) elem_pass_kernel(ElemPass a) {
     }
 }
 
-size_t pass_lds(const ElemPass& a) {
-    const int rows = 4 * a.ksteps > 16 * a.nwaves ? 4 * a.ksteps : 16 * a.nwaves;
+// LDS of a pass: the staged inputs (4 ksteps rows), or the M output rows when a column pass
+// stores element-major values through the tile.
+size_t pass_lds(const ElemPass& a, bool rows_pass) {
+    int rows = 4 * a.ksteps;
+    if (!rows_pass && a.aout.layout == AX_VALUES && a.M > rows) rows = a.M;
     return (size_t)rows * kStride * sizeof(double);
 }
 
@@ -228,19 +282,21 @@ hipError_t launch_ks(const ElemPass& a, hipStream_t s) {
     }
     const dim3 block((unsigned)(64 * a.nwaves));
     if (ROWS && a.tab2)  // two products: fragments streamed (registers would spill)
-        hipLaunchKernelGGL((elem_pass_kernel<0, true, true>), grid, block, pass_lds(a), s, a);
+        hipLaunchKernelGGL((elem_pass_kernel<0, true, true>), grid, block, pass_lds(a, ROWS), s, a);
     else if (ROWS)
-        hipLaunchKernelGGL((elem_pass_kernel<KS, true, false>), grid, block, pass_lds(a), s, a);
+        hipLaunchKernelGGL((elem_pass_kernel<KS, true, false>), grid, block, pass_lds(a, ROWS), s, a);
     else
-        hipLaunchKernelGGL((elem_pass_kernel<KS, false, false>), grid, block, pass_lds(a), s, a);
+        hipLaunchKernelGGL((elem_pass_kernel<KS, false, false>), grid, block, pass_lds(a, ROWS), s, a);
     return hipGetLastError();
 }
 
 template <bool ROWS>
 hipError_t launch_pass(const ElemPass& a, hipStream_t s) {
     if (a.lines <= 0 || a.ain.n <= 0) return hipSuccess;
-    if ((!ROWS && a.tab2) || a.nwaves < 1 || 16 * a.nwaves < a.M || a.nwaves > 16 || a.ksteps < 1 ||
-        4 * a.ksteps < a.L || a.ksteps > kMaxKsteps || pass_lds(a) > 160 * 1024 || a.ain.n != a.aout.n)
+    const bool tail_ok = a.tail == 0 || (a.tail <= 4 && a.nwaves >= 4 && a.ttab && (!a.tab2 || a.ttab2));
+    if ((!ROWS && a.tab2) || a.nwaves < 1 || 16 * a.nwaves + a.tail < a.M || a.nwaves > 16 || !tail_ok ||
+        a.ksteps < 1 || 4 * a.ksteps < a.L || a.ksteps > kMaxKsteps || pass_lds(a, ROWS) > 160 * 1024 ||
+        a.ain.n != a.aout.n)
         return hipErrorInvalidValue;
     // the k-steps of the product, rounded up to a compiled count (fragments in registers),
     // or streamed beyond 33
