@@ -341,19 +341,20 @@ __device__ __forceinline__ void residual_rows(const DimDev& dx, const Residual& 
     }
 }
 
+constexpr int kResRows = 4;  // rows per block: short-lived blocks, every load of a block in flight at once
 __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     __shared__ double red[3][4];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    // band 0 is the hats; the bubbles are split into gridDim.y - 1 bands
-    const int nb = dx.N - dx.nh, bands = gridDim.y - 1;
+    // bands of kResRows rows: first the hat rows, then the bubble rows
+    const int hb = (dx.nh + kResRows - 1) / kResRows;
     double sr = 0.0, sg = 0.0, su = 0.0;
     if (j < a.ncols) {
-        if (blockIdx.y == 0) {
-            residual_rows<7>(dx, a, j, 0, dx.nh, sr, sg, su);
+        if ((int)blockIdx.y < hb) {
+            const int ibeg = blockIdx.y * kResRows;
+            residual_rows<7>(dx, a, j, ibeg, min(dx.nh, ibeg + kResRows), sr, sg, su);
         } else {
-            const int rpb = (nb + bands - 1) / bands;
-            const int ibeg = dx.nh + (blockIdx.y - 1) * rpb, iend = min(dx.N, ibeg + rpb);
-            residual_rows<5>(dx, a, j, ibeg, iend, sr, sg, su);
+            const int ibeg = dx.nh + (blockIdx.y - hb) * kResRows;
+            residual_rows<5>(dx, a, j, ibeg, min(dx.N, ibeg + kResRows), sr, sg, su);
         }
     }
     if (a.norm_acc) {
@@ -382,17 +383,32 @@ __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     }
 }
 
-// norm_acc[k] += sum of the residual's per-block partial sums k (one workgroup, fixed order).
-__global__ void __launch_bounds__(256) residual_reduce(const double* __restrict__ partials, int nblk, int nk,
-                                                       double* norm_acc) {
+// Two-stage sum of the residual's per-block partial sums (fixed order, deterministic):
+// stage 1, block g of kReduceBlocks: out[k * kReduceBlocks + g] = sum over b = g (mod
+// kReduceBlocks) of partials[k][b]; stage 2 (one block): norm_acc[k] += sum over g.
+constexpr int kReduceBlocks = 128;
+__global__ void __launch_bounds__(256) residual_reduce1(const double* __restrict__ partials, int nblk, int nk,
+                                                        double* __restrict__ out) {
     __shared__ double red[4];
     for (int k = 0; k < nk; ++k) {
         double t = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) t += partials[(long)k * nblk + b];
+        for (int b = blockIdx.x + kReduceBlocks * threadIdx.x; b < nblk; b += kReduceBlocks * blockDim.x)
+            t += partials[(long)k * nblk + b];
         t = wave_sum(t);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
         __syncthreads();
-        if (threadIdx.x == 0) norm_acc[k] += red[0] + red[1] + red[2] + red[3];
+        if (threadIdx.x == 0) out[k * kReduceBlocks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        __syncthreads();
+    }
+}
+__global__ void __launch_bounds__(kReduceBlocks) residual_reduce2(const double* __restrict__ part1, int nk,
+                                                                  double* norm_acc) {
+    __shared__ double red[2];
+    for (int k = 0; k < nk; ++k) {
+        double t = wave_sum(part1[k * kReduceBlocks + threadIdx.x]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) norm_acc[k] += red[0] + red[1];
         __syncthreads();
     }
 }
@@ -486,16 +502,16 @@ hipError_t launch_op_apply(const DimDev& d, const OpApply& a, bool column, hipSt
     return hipGetLastError();
 }
 
-// One band of hat rows, then bands of about 32 bubble rows; 256 columns per block.
+// Bands of kResRows hat rows, then of kResRows bubble rows; 256 columns per block.
 static dim3 residual_grid(const DimDev& dx, int ncols) {
     const int nb = dx.N - dx.nh;
-    const int bands = nb <= 0 ? 0 : (nb + 31) / 32;
-    return dim3((unsigned)((ncols + 255) / 256), (unsigned)(1 + bands));
+    const int bands = (dx.nh + kResRows - 1) / kResRows + (nb + kResRows - 1) / kResRows;
+    return dim3((unsigned)((ncols + 255) / 256), (unsigned)bands);
 }
 
 long residual_partials(const DimDev& dx, int ncols) {
     const dim3 g = residual_grid(dx, ncols);
-    return 3L * g.x * g.y;
+    return 3L * g.x * g.y + 3L * kReduceBlocks;  // per-block sums, then the first reduction stage
 }
 
 hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s) {
@@ -504,8 +520,12 @@ hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s) {
     hipLaunchKernelGGL(residual_kernel, g, dim3(256), 0, s, dx, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.norm_acc || !a.partials) return e;
-    hipLaunchKernelGGL(residual_reduce, dim3(1), dim3(256), 0, s, a.partials, (int)(g.x * g.y), a.U ? 3 : 2,
-                       a.norm_acc);
+    const int nblk = (int)(g.x * g.y), nk = a.U ? 3 : 2;
+    double* stage1 = a.partials + 3L * nblk;
+    hipLaunchKernelGGL(residual_reduce1, dim3(kReduceBlocks), dim3(256), 0, s, a.partials, nblk, nk, stage1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(residual_reduce2, dim3(1), dim3(kReduceBlocks), 0, s, stage1, nk, a.norm_acc);
     return hipGetLastError();
 }
 
