@@ -199,34 +199,7 @@ __device__ __forceinline__ void gather_km(const DimDev& d, const double* x, long
     }
 }
 
-// Row operator: lines are rows (contiguous positions); thread x -> position, and a block
-// takes kRowLines consecutive lines (fewer, longer workgroups: one line each made the
-// launch dispatch-bound).
-constexpr int kRowLines = 8;
-__global__ void __launch_bounds__(256) op_apply_rows(DimDev d, OpApply a) {
-    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-    const int l0 = blockIdx.y * kRowLines;
-    if (pos >= d.N) return;
-    for (int line = l0; line < min(l0 + kRowLines, a.nlines); ++line) {
-        double Kx, Mx;
-        gather_km(d, a.in + (long)line * a.in_sl, a.in_sp, pos, Kx, Mx);
-        a.out1[(long)line * a.o1_sl + (long)pos * a.o1_sp] = a.k1 * Kx + a.t1 * Mx;
-        if (a.out2) a.out2[(long)line * a.o2_sl + (long)pos * a.o2_sp] = a.k2 * Kx + a.t2 * Mx;
-    }
-}
-
-// Column operator: lines are columns; thread x -> line (contiguous), y -> position.
-__global__ void __launch_bounds__(256) op_apply_cols(DimDev d, OpApply a) {
-    const int line = blockIdx.x * blockDim.x + threadIdx.x;
-    const int pos = blockIdx.y;
-    if (pos >= d.N || line >= a.nlines) return;
-    double Kx, Mx;
-    gather_km(d, a.in + (long)line * a.in_sl, a.in_sp, pos, Kx, Mx);
-    a.out1[(long)line * a.o1_sl + (long)pos * a.o1_sp] = a.k1 * Kx + a.t1 * Mx;
-    if (a.out2) a.out2[(long)line * a.o2_sl + (long)pos * a.o2_sp] = a.k2 * Kx + a.t2 * Mx;
-}
-
-// The x-direction stencil of K and M at one position as a fixed number of taps (App. A
+// The stencil of K and M at one position of a line as a fixed number of taps (App. A
 // entries): K x = sum_t kc[t] x[idx[t]], M x = sum_t mc[t] x[idx[t]].  Absent taps point at
 // the position itself with zero coefficients, and every choice is a select, not a branch,
 // so that the loads of several positions can be in flight together.  Hat rows have 7 taps
@@ -295,6 +268,48 @@ __device__ __forceinline__ void bubble_taps(const DimDev& d, int pos, Taps<5>& t
 __device__ __forceinline__ void make_taps(const DimDev& d, int pos, Taps<7>& t) { hat_taps(d, pos, t); }
 __device__ __forceinline__ void make_taps(const DimDev& d, int pos, Taps<5>& t) { bubble_taps(d, pos, t); }
 
+// Row operator: lines are rows (contiguous positions); thread x -> position, and a block
+// takes kRowLines consecutive lines.  The position's stencil taps are computed once (they do
+// not depend on the line) and every load of a line is independent of the others.
+constexpr int kRowLines = 8;
+template <int NT>
+__device__ __forceinline__ void apply_rows_taps(const DimDev& d, const OpApply& a, int pos, int l0) {
+    Taps<NT> t;
+    make_taps(d, pos, t);
+    const int l1 = min(l0 + kRowLines, a.nlines);
+    for (int line = l0; line < l1; ++line) {
+        const double* x = a.in + (long)line * a.in_sl;
+        double Kx = 0.0, Mx = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const double v = x[(long)t.idx[q] * a.in_sp];
+            Kx += t.kc[q] * v;
+            Mx += t.mc[q] * v;
+        }
+        a.out1[(long)line * a.o1_sl + (long)pos * a.o1_sp] = a.k1 * Kx + a.t1 * Mx;
+        if (a.out2) a.out2[(long)line * a.o2_sl + (long)pos * a.o2_sp] = a.k2 * Kx + a.t2 * Mx;
+    }
+}
+__global__ void __launch_bounds__(256) op_apply_rows(DimDev d, OpApply a) {
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    const int l0 = blockIdx.y * kRowLines;
+    if (pos >= d.N) return;
+    if (pos < d.nh) apply_rows_taps<7>(d, a, pos, l0);
+    else apply_rows_taps<5>(d, a, pos, l0);
+}
+
+// Column operator: lines are columns; thread x -> line (contiguous), y -> position.
+__global__ void __launch_bounds__(256) op_apply_cols(DimDev d, OpApply a) {
+    const int line = blockIdx.x * blockDim.x + threadIdx.x;
+    const int pos = blockIdx.y;
+    if (pos >= d.N || line >= a.nlines) return;
+    double Kx, Mx;
+    gather_km(d, a.in + (long)line * a.in_sl, a.in_sp, pos, Kx, Mx);
+    a.out1[(long)line * a.o1_sl + (long)pos * a.o1_sp] = a.k1 * Kx + a.t1 * Mx;
+    if (a.out2) a.out2[(long)line * a.o2_sl + (long)pos * a.o2_sp] = a.k2 * Kx + a.t2 * Mx;
+}
+
+
 // r[i][j] = alpha G[i][j] + beta ((ax_k K + ax_t M) T1 + M T2)[i][j], operators along x.
 // A block owns 256 columns and a band of rows, all hats (7-tap rows) or all bubbles (5-tap
 // rows); a thread takes RU rows at a time, whose taps are the same for every lane, and
@@ -345,7 +360,10 @@ constexpr int kResRows = 4;  // rows per block: short-lived blocks, every load o
 __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     __shared__ double red[3][4];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    // bands of kResRows rows: first the hat rows, then the bubble rows
+    // bands of kResRows rows: first the hat rows, then the bubble rows, in address order.
+    // (Bands ordered element block by element block, all degrees of a block in turn, cut the
+    // HBM reads of the m -/+ 2 rows from 1.67x to 1.05x of the algorithmic bytes but took 377
+    // instead of 305 us at N = 4095: consecutive workgroups then touch rows 2 MB apart.)
     const int hb = (dx.nh + kResRows - 1) / kResRows;
     double sr = 0.0, sg = 0.0, su = 0.0;
     if (j < a.ncols) {
