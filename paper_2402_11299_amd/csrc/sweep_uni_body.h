@@ -2,13 +2,10 @@
 // method and the general kernel).
 //
 // On a mesh of equal elements the factor and operator entries depend only on the
-// degree m, so they are read from one per-degree record table through the scalar
-// cache; with n a multiple of the chains per wavefront every wavefront has one
-// parity, so those reads are wavefront-uniform.  (Copies of the table held one chain
-// step per lane and read back with readlane ran the FP32 column half-sweep 7% faster,
-// but a lane copy is only valid where the whole wavefront wrote it: lanes of missing
-// lines, masked off by their branch, left stale copies that gave NaN on 8-line
-// workgroups of p = 128.  They are not used.)  The chain length is a
+// degree m, so they come from one per-degree record table; with n a multiple of the
+// chains per wavefront every wavefront has one parity, so they are wavefront-uniform
+// (read through the scalar cache, or from lane copies in the FP32-storage ADI
+// recurrences).  The chain length is a
 // compile-time constant CL = p/2; a chain one degree shorter (odd parity, even
 // p) is padded by a phantom degree whose coefficients are zero, which makes it
 // inert in every recurrence, so the unrolled chain loops carry no per-step
@@ -126,6 +123,36 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     const cptr pt = (cptr)(a.ptab);
     auto PT = [&](int m, int k) -> double { return pt[m * 16 + k]; };
 
+    // FP32 storage: the ADI recurrences take their per-step coefficients from lane copies
+    // (lane s holds the coefficient of chain step s, degree pi + 2s, read back with
+    // readlane), so the unrolled chains do not wait on a scalar load at every step.  A copy
+    // is valid only where the whole wavefront wrote it: the copies are loaded outside every
+    // lane-dependent branch and pinned there by an empty asm that consumes them, so the
+    // compiler cannot sink the loads into a branch that masks off lanes (lanes of missing
+    // lines would then keep stale copies).  FP64 storage keeps the scalar loads: its chain
+    // and G~ registers leave no room for the copies.
+    constexpr bool kLaneCoef = sizeof(TIN) == 4 && (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE);
+    auto lane_coef = [&](int k) -> double { return lane < CL ? a.ptab[(pi + 2 * lane) * 16 + k] : 0.0; };
+    auto pin = [](double& v) { asm volatile("" : "+v"(v)); };
+    auto RL = [&](double v, int s, int k) -> double {
+        if constexpr (!kLaneCoef) {
+            (void)v;
+            return PT(pi + 2 * s, k);
+        } else {
+            const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+            return __hiloint2double(hi, lo);
+        }
+    };
+    // issued ahead of the chain loads: loads complete in order, so waiting for these
+    // does not wait for the chains
+    double cb0 = 0.0, cb1 = 0.0, cb2 = 0.0;
+    if constexpr (kLaneCoef) {
+        cb0 = lane_coef(0);
+        cb1 = lane_coef(1);
+        cb2 = lane_coef(2);
+    }
+
     auto IDX = [&](const Layout& L, int ln, int pos) -> long { return COL ? addr(L, pos, ln) : addr(L, ln, pos); };
     // byte offset of chain step 0 and byte stride per step (32-bit: loads and stores
     // address a uniform base plus a per-lane 32-bit offset)
@@ -136,25 +163,32 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     };
 
     const char* inb = reinterpret_cast<const char*>(a.in);
+    const TIN* in = reinterpret_cast<const TIN*>(a.in);
+    // the hat entry of the lane, issued ahead of the chains (loads complete in order, so
+    // its LDS write below waits for it alone); lanes without one read entry 0
+    const bool has_hat = act && c < nh;
+    const TIN hat_in = in[has_hat ? IDX(a.lin, line, c) : 0];
     double y[CL];
     if (act) {
-        // issued highest degree first: the first recurrence consumes them in that order
+        // issued highest degree first: the first recurrence consumes them in that order;
+        // no load sits in a branch of its own (its wait would come before the next issue):
+        // the phantom degree reads the step below it and drops the value
         unsigned o, st;
         chain0(a.lin, o, st, sizeof(TIN));
         o += (CL - 1) * st;
-        y[CL - 1] = full ? (double)*reinterpret_cast<const TIN*>(inb + o) : 0.0;
+        const TIN top = *reinterpret_cast<const TIN*>(inb + (full ? o : o - st));
+        y[CL - 1] = full ? (double)top : 0.0;
 #pragma unroll
         for (int s = CL - 2; s >= 0; --s) {
             o -= st;
             y[s] = (double)*reinterpret_cast<const TIN*>(inb + o);
         }
     }
-    const TIN* in = reinterpret_cast<const TIN*>(a.in);
     double* A = sA + l * hs;
     double* B = sB + l * hs;
     double* H1 = sH1 + l * 2 * n;
     double* H2 = sH2 + l * 2 * n;
-    if (act && c < nh) A[c] = (double)in[IDX(a.lin, line, c)];
+    if (has_hat) A[c] = (double)hat_in;
 
     auto for_my_lines = [&](auto&& body) {
         for (int ll = wave; ll < LW; ll += nwaves) {
@@ -175,6 +209,11 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     };
 
     if (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE) {
+        if constexpr (kLaneCoef) {
+            pin(cb0);
+            pin(cb1);
+            pin(cb2);
+        }
         // z = Lm^T y and the back substitution of S^{-1} z, fused (highest degree first):
         // y'_s = b1 y_s + b2 y_{s+1} + b3 y'_{s+1}
         if (act) {
@@ -183,14 +222,19 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             for (int s = CL - 1; s >= 0; --s) {
                 const int m = pi + 2 * s;
                 const double yo = y[s];
-                double yp = PT(m, 0) * yo;
-                if (s + 1 < CL) yp += PT(m, 1) * yo_n + PT(m, 2) * yp_n;
+                double yp = RL(cb0, s, 0) * yo;
+                if (s + 1 < CL) yp += RL(cb1, s, 1) * yo_n + RL(cb2, s, 2) * yp_n;
                 y[s] = yp;
                 yo_n = yo;
                 yp_n = yp;
             }
             H1[c] = yo_n;
             H2[c] = yp_n;
+        }
+        double cf3 = 0.0, cf4 = 0.0;
+        if constexpr (kLaneCoef) {
+            cf3 = lane_coef(3);
+            cf4 = lane_coef(4);
         }
         __syncthreads();
         for_my_lines([&](int ll) {
@@ -210,6 +254,10 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             hat_forward(A2, FS, nh, lane);
         });
         __syncthreads();
+        if constexpr (kLaneCoef) {
+            pin(cf3);
+            pin(cf4);
+        }
         double xl = 0.0, xr = 0.0;
         if (act) {
             if (vhat(d.bc, n, e)) xl = A[hov(d.bc, e)];
@@ -219,8 +267,8 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
 #pragma unroll
             for (int s = 0; s < CL; ++s) {
                 const int m = pi + 2 * s;
-                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * PT(m, 3);
-                else prev = PT(m, 3) * y[s] + PT(m, 4) * prev;
+                if (s == 0) prev = (y[0] - FS.cpl[4 * e + 2 * pi] * xl - FS.cpl[4 * e + 2 * pi + 1] * xr) * RL(cf3, 0, 3);
+                else prev = RL(cf3, s, 3) * y[s] + RL(cf4, s, 4) * prev;
                 y[s] = prev;
             }
             H1[c] = y[0];
@@ -270,7 +318,7 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             gv[s] = *reinterpret_cast<const TIN*>(gb + (real ? og0 + (unsigned)s * sg : 0u));
         };
 #pragma unroll
-        for (int s = CL - PF; s < CL; ++s) load_g(s);
+        for (int s = CL - 1; s >= CL - PF; --s) load_g(s);  // in the order they are consumed
         if (act) {
             char* ob = reinterpret_cast<char*>(a.out);
             unsigned oo, so;
@@ -283,7 +331,7 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             for (int s = CL - 1; s >= 0; --s) {
                 if (PF < CL && s == CL - PF) {
 #pragma unroll
-                    for (int s2 = 0; s2 < CL - PF; ++s2) load_g(s2);
+                    for (int s2 = CL - PF - 1; s2 >= 0; --s2) load_g(s2);
                 }
                 const int m = pi + 2 * s;
                 const double x = y[s];
@@ -298,6 +346,11 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             }
             H2[c] = u_n;
         }
+        // G~ of the lane's hat, issued before the hat block (its latency hides there)
+        const TIN g_hat = reinterpret_cast<const TIN*>(a.g)[has_hat ? IDX(a.lg, line, c) : 0];
+        // equal elements: one width (through the scalar cache, so that the hat block
+        // waits on no vector load, which would also wait for the stores above)
+        const double dq = ((cptr)d.delta)[0], idq = ((cptr)d.invdelta)[0];
         __syncthreads();
         for_my_lines([&](int ll) {
             double* A2 = sA + ll * hs;
@@ -310,14 +363,12 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
                 double r = kap * robin_at(d, v) * xh;
                 if (v >= 1) {
                     const int q = v - 1;
-                    const double dq = d.delta[q], idq = d.invdelta[q];
                     r += (kap * idq + tau * dq * (1.0 / 3.0)) * xh;
                     if (vhat(d.bc, n, v - 1)) r += (-kap * idq + tau * dq * (1.0 / 6.0)) * A2[h - 1];
                     r += tau * dq * (hx[q] * (1.0 / 6.0) + hx[n + q] * (1.0 / 30.0));
                 }
                 if (v <= n - 1) {
                     const int q = v;
-                    const double dq = d.delta[q], idq = d.invdelta[q];
                     r += (kap * idq + tau * dq * (1.0 / 3.0)) * xh;
                     if (vhat(d.bc, n, v + 1)) r += (-kap * idq + tau * dq * (1.0 / 6.0)) * A2[h + 1];
                     r += tau * dq * (hx[q] * (1.0 / 6.0) - hx[n + q] * (1.0 / 30.0));
@@ -328,10 +379,9 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
             hat_backward(B2, FM, nh, lane);
         });
         __syncthreads();
-        if (act && c < nh) {
-            const TIN* g = reinterpret_cast<const TIN*>(a.g);
+        if (has_hat) {
             TOUT* out = reinterpret_cast<TOUT*>(a.out);
-            out[IDX(a.lout, line, c)] = (TOUT)((double)g[IDX(a.lg, line, c)] - B[c]);
+            out[IDX(a.lout, line, c)] = (TOUT)((double)g_hat - B[c]);
         }
         return;
     }

@@ -27,7 +27,7 @@ struct AxisMap {
 // operands of v_mfma_f64_16x16x4f64: tab[((w S + s) 64 + lane)] = Mat[16 w + lane % 16]
 // [4 s + lane / 16] (zero outside M x L), w < ceil(M / 16), s < ksteps = ceil(L / 4).
 // A workgroup of nwaves waves stages the inputs of 64 lines in LDS (max(4 ksteps, 16 nwaves)
-// x 80 doubles, at most 160 KiB).  With tab2 set (Burgers epilogue, row passes only) a
+// rows of 65 doubles, under 160 KiB).  With tab2 set (Burgers epilogue, row passes only) a
 // second matrix scaled per element by scale2[e] gives w = tab2 . in, and the pass stores
 // v - dt w v.
 struct ElemPass {
