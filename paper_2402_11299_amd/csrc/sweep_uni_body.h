@@ -54,7 +54,8 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     FM.cpl = FM.link0 + hs;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform: scalar registers
     const int nwaves = blockDim.x >> 6;
     int c, l;
     if (COL) {
@@ -123,15 +124,16 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     const cptr pt = (cptr)(a.ptab);
     auto PT = [&](int m, int k) -> double { return pt[m * 16 + k]; };
 
-    // FP32 storage: the ADI recurrences take their per-step coefficients from lane copies
-    // (lane s holds the coefficient of chain step s, degree pi + 2s, read back with
-    // readlane), so the unrolled chains do not wait on a scalar load at every step.  A copy
-    // is valid only where the whole wavefront wrote it: the copies are loaded outside every
-    // lane-dependent branch and pinned there by an empty asm that consumes them, so the
-    // compiler cannot sink the loads into a branch that masks off lanes (lanes of missing
-    // lines would then keep stale copies).  FP64 storage keeps the scalar loads: its chain
-    // and G~ registers leave no room for the copies.
-    constexpr bool kLaneCoef = sizeof(TIN) == 4 && (MODE == SWEEP_FULL || MODE == SWEEP_SOLVE);
+    // Full half-sweeps with chains of 32 or more steps: the two chain recurrences take their
+    // per-step coefficients from lane copies (lane s holds the coefficient of chain step s,
+    // degree pi + 2s, read back with readlane), so the unrolled chains do not wait on a
+    // scalar load at every step.  A copy is valid only where the whole wavefront wrote it:
+    // the copies are loaded outside every lane-dependent branch and pinned there by an
+    // empty asm that consumes them, so the compiler cannot sink the loads into a branch
+    // that masks off lanes (lanes of missing lines would then keep stale copies).  Shorter
+    // chains keep the scalar loads (the compiler hoists all their readlanes and spills
+    // scalar registers).
+    constexpr bool kLaneCoef = MODE == SWEEP_FULL && CL >= 32;
     auto lane_coef = [&](int k) -> double { return lane < CL ? a.ptab[(pi + 2 * lane) * 16 + k] : 0.0; };
     auto pin = [](double& v) { asm volatile("" : "+v"(v)); };
     auto RL = [&](double v, int s, int k) -> double {
