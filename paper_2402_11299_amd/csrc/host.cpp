@@ -614,12 +614,15 @@ hpadi::Layout user_layout(const hpadi_plan_s* P, long ld) {
     return L;
 }
 
-// A row pass reading a panel layout whose rows are narrower than a 128-byte line per
-// workgroup (lines per workgroup x panel width x element size < 128) gets an XCD-aware
-// workgroup order: the workgroups sharing each line run on one XCD.
+// Workgroups that share cache lines of a panel layout get an XCD-aware order (the
+// workgroups sharing each line run on one XCD in consecutive dispatch slots): a row pass
+// whose workgroup rows are narrower than a 128-byte line (lines per workgroup x panel
+// width x element size < 128), a column pass whose workgroup covers fewer lines than a
+// panel holds (the workgroups of one panel share every sector).
 hpadi::SweepArgs with_xcd_group(hpadi::SweepArgs a, bool column, int tin) {
     const int w = a.lpb * a.lin.panel * tin;
-    a.xcd_group = (!column && a.lin.panel > 0 && w > 0 && w < 128) ? 128 / w : 1;
+    if (column) a.xcd_group = (a.lin.panel > 0 && a.lpb > 0 && a.lpb < a.lin.panel) ? a.lin.panel / a.lpb : 1;
+    else a.xcd_group = (a.lin.panel > 0 && w > 0 && w < 128) ? 128 / w : 1;
     return a;
 }
 

@@ -86,27 +86,19 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
         FM.cpl[i] = Mf[fl.off_cpl + i];
     }
 
-    // One line per workgroup in a column pass: the 8 columns of a panel share every
-    // 32-byte sector, so their workgroups are placed on one XCD (workgroup b runs on
-    // XCD b mod 8) in consecutive dispatch slots, where they share that XCD's L2.
+    // Workgroups that share cache lines (a row pass covering only part of each 128-byte
+    // line of a panel, e.g. 4 rows of 16 bytes in FP32; a column pass covering fewer
+    // columns than a panel holds, whose workgroups share every sector) are xcd_group
+    // consecutive workgroups: they run on one XCD (workgroup b runs on XCD b mod 8) in
+    // consecutive dispatch slots, so each line is fetched into that XCD's L2 once
+    // instead of once per XCD.
     int blk = bid;
-    if (standalone && !COL && a.xcd_group > 1) {
-        // A row pass whose workgroup covers only part of each 128-byte line of a panel
-        // (4 rows of 16 bytes in FP32): the xcd_group workgroups sharing those lines run
-        // on one XCD in consecutive dispatch slots, so the line is fetched into that
-        // XCD's L2 once instead of once per XCD.
+    if (standalone && a.xcd_group > 1) {
         const int g = a.xcd_group;
         const int full = (nblk / (8 * g)) * (8 * g);
         if (blk < full) {
             const int xcd = blk % 8, slot = blk / 8;
             blk = (slot / g) * (8 * g) + xcd * g + slot % g;
-        }
-    }
-    if (standalone && LW == 1 && COL) {
-        const int full = (nblk / 64) * 64;
-        if (blk < full) {
-            const int xcd = blk % 8, slot = blk / 8;
-            blk = ((slot / 8) * 8 + xcd) * 8 + slot % 8;
         }
     }
     auto line_of = [&](int ll) -> int {
