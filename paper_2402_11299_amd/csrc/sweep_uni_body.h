@@ -128,14 +128,28 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
     constexpr bool kLaneCoef = MODE == SWEEP_FULL && CL >= 32;
     auto lane_coef = [&](int k) -> double { return lane < CL ? a.ptab[(pi + 2 * lane) * 16 + k] : 0.0; };
     auto pin = [](double& v) { asm volatile("" : "+v"(v)); };
+    auto lane_read = [](double v, int s) -> double {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+        return __hiloint2double(hi, lo);
+    };
     auto RL = [&](double v, int s, int k) -> double {
         if constexpr (!kLaneCoef) {
             (void)v;
             return PT(pi + 2 * s, k);
         } else {
-            const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
-            const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
-            return __hiloint2double(hi, lo);
+            return lane_read(v, s);
+        }
+    };
+    // the transform passes take the two coefficients of their one recurrence the same way
+    // (the final pass keeps the scalar loads: its registers hold the previous solution too)
+    constexpr bool kLaneT = MODE == SWEEP_TRANSFORM && CL >= 32;
+    auto RT = [&](double v, int s, int k) -> double {
+        if constexpr (!kLaneT) {
+            (void)v;
+            return PT(pi + 2 * s, k);
+        } else {
+            return lane_read(v, s);
         }
     };
     // issued ahead of the chain loads: loads complete in order, so waiting for these
@@ -145,6 +159,11 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
         cb0 = lane_coef(0);
         cb1 = lane_coef(1);
         cb2 = lane_coef(2);
+    }
+    double ct0 = 0.0, ct1 = 0.0;
+    if constexpr (kLaneT) {
+        ct0 = lane_coef(9);
+        ct1 = lane_coef(11);
     }
 
     auto IDX = [&](const Layout& L, int ln, int pos) -> long { return COL ? addr(L, pos, ln) : addr(L, ln, pos); };
@@ -380,6 +399,10 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
         return;
     }
 
+    if constexpr (kLaneT) {
+        pin(ct0);
+        pin(ct1);
+    }
     if (MODE == SWEEP_TRANSFORM) {
         // u = Lm^{-T} y: chain back substitution (entries final as computed, stored at once),
         // then the hat block
@@ -392,7 +415,7 @@ __device__ __forceinline__ void sweep_uni_body(const DimDev& d, const SweepArgs&
 #pragma unroll
             for (int s = CL - 1; s >= 0; --s) {
                 const int m = pi + 2 * s;
-                u_n = PT(m, 9) * y[s] + (s + 1 < CL ? PT(m, 11) * u_n : 0.0);
+                u_n = RT(ct0, s, 9) * y[s] + (s + 1 < CL ? RT(ct1, s, 11) * u_n : 0.0);
                 if (s < CL - 1 || full) *reinterpret_cast<TOUT*>(ob + oo) = (TOUT)u_n;
                 oo -= so;
             }
