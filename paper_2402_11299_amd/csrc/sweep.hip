@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
     double* scf = FM.cpl + 4 * n;  // uniform meshes: per-degree records, 8 (p-1) doubles
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront-uniform: scalar registers
     const int nwaves = blockDim.x >> 6;
     int c, l;
     if (COL) {
@@ -145,13 +146,20 @@ __global__ void __launch_bounds__(sweep_max_threads(CL)) sweep_kernel(DimDev d, 
     }
     auto in_at = [&](int s) -> long { return UNI ? oi + s * si : chain_off(a.lin, s); };
 
+    // the hat entry first, then the chain; no load sits in a branch of its own (its wait
+    // would come before the next load is issued): steps past the chain read step 0 and
+    // are set to zero
+    const bool has_hat = act && c < nh;
+    const TIN hat_in = in[has_hat ? IDX(a.lin, line, c) : 0];
     double y[CL];
     if (act) {
 #pragma unroll
-        for (int s = 0; s < CL; ++s)
-            if (s < len) y[s] = (double)in[in_at(s)];
-        if (c < nh) A[c] = (double)in[IDX(a.lin, line, c)];
+        for (int s = 0; s < CL; ++s) {
+            const TIN v = in[s < len ? in_at(s) : in_at(0)];
+            y[s] = s < len ? (double)v : 0.0;
+        }
     }
+    if (has_hat) A[c] = (double)hat_in;
     if (UNI) __syncthreads();  // staged per-degree records
 
     // The scanning wavefront of a line: wave w handles lines w, w + nwaves, ...
