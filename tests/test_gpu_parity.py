@@ -72,7 +72,8 @@ def test_factor_matches_oracle(hp, torch, n, p, bc, w2):
 
 
 @pytest.mark.parametrize("nx,px,ny,py,bc", [(4, 8, 4, 8, "dirichlet"), (3, 7, 5, 6, "neumann"),
-                                            (1, 2, 2, 3, "neumann"), (32, 32, 32, 32, "dirichlet")])
+                                            (1, 2, 2, 3, "neumann"), (32, 32, 32, 32, "dirichlet"),
+                                            (16, 32, 12, 24, "neumann")])
 def test_load_and_apply_match_oracle(hp, torch, nx, px, ny, py, bc):
     print(f"load/apply case {nx},{px},{ny},{py},{bc}", flush=True)
     x, y = hp.Op1D(nx, px, 0, 1, bc), hp.Op1D(ny, py, 0, 2, bc)
