@@ -4,8 +4,8 @@
 // On a mesh of equal elements the factor and operator entries depend only on the
 // degree m, so they come from one per-degree record table; with n a multiple of the
 // chains per wavefront every wavefront has one parity, so they are wavefront-uniform
-// (read through the scalar cache, or from lane copies in the FP32-storage ADI
-// recurrences).  The chain length is a
+// (read through the scalar cache, or from lane copies in the chain recurrences of the
+// full half-sweeps and the transform passes).  The chain length is a
 // compile-time constant CL = p/2; a chain one degree shorter (odd parity, even
 // p) is padded by a phantom degree whose coefficients are zero, which makes it
 // inert in every recurrence, so the unrolled chain loops carry no per-step
