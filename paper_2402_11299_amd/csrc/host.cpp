@@ -591,7 +591,7 @@ void family_free(ShiftFamily& F) {
 void plan_free(hpadi_plan_s* P) {
     if (!P) return;
     for (ShiftFamily& F : P->fam) family_free(F);
-    for (void* q : {P->Wk, P->Gt, (void*)P->T64, (void*)P->T1, (void*)P->T2, (void*)P->R64,
+    for (void* q : {P->Wk, P->Gt, (void*)P->T64, (void*)P->T12, (void*)P->R64,
                     (void*)P->H, (void*)P->acc, (void*)P->part})
         if (q) hipFree(q);
     if (P->acc_host) hipHostFree(P->acc_host);
@@ -785,20 +785,21 @@ double lemma_bound(double eps, double d2, double u2) {
     return lo > 0.0 ? std::max(f * nd / lo, kRoundingFloor) : std::numeric_limits<double>::infinity();
 }
 
-// T1 = U M_y, T2 = U A_y (row operators, FP64).
+// T1 = U M_y, T2 = U A_y (row operators, FP64), interleaved as (T1, T2) pairs in P->T12
+// (the residual reads both at every tap: one 16-byte load).
 int row_products(hpadi_plan_s* P, const double* U, long ldu) {
     hpadi::OpApply a{};
     a.in = U;
     a.in_sl = ldu;
     a.in_sp = 1;
-    a.out1 = P->T1;
-    a.o1_sl = P->ldw;
-    a.o1_sp = 1;
+    a.out1 = P->T12;
+    a.o1_sl = 2 * P->ldw;
+    a.o1_sp = 2;
     a.k1 = 0.0;
     a.t1 = 1.0;
-    a.out2 = P->T2;
-    a.o2_sl = P->ldw;
-    a.o2_sp = 1;
+    a.out2 = P->T12 + 1;
+    a.o2_sl = 2 * P->ldw;
+    a.o2_sp = 2;
     a.k2 = P->ky;
     a.t2 = P->sy;
     a.nlines = P->dx.op.N;
@@ -807,8 +808,7 @@ int row_products(hpadi_plan_s* P, const double* U, long ldu) {
 
 int ensure_fp64_work(hpadi_plan_s* P) {
     const size_t cnt = (size_t)P->dx.op.N * P->ldw;
-    if (!P->T1 && dmalloc(&P->T1, cnt) != hipSuccess) return HPADI_ENOMEM;
-    if (!P->T2 && dmalloc(&P->T2, cnt) != hipSuccess) return HPADI_ENOMEM;
+    if (!P->T12 && dmalloc(&P->T12, 2 * cnt) != hipSuccess) return HPADI_ENOMEM;
     return HPADI_OK;
 }
 
@@ -822,8 +822,8 @@ int residual_into_r64(hpadi_plan_s* P, const double* G, long ldg, const double* 
     hpadi::Residual r{};
     r.G = G;
     r.g_ld = ldg;
-    r.T1 = P->T1;
-    r.T2 = P->T2;
+    r.T1 = P->T12;
+    r.T2 = nullptr;
     r.t_ld = P->ldw;
     r.r64 = P->R64;
     r.r64_ld = P->ldw;
@@ -1410,8 +1410,8 @@ int hpadi_apply(hpadi_plan P, const double* U, int ldu, double* Y, int ldy) {
     if ((rc = row_products(P, U, ldu)) != HPADI_OK) return rc;
     hpadi::Residual r{};
     r.G = nullptr;
-    r.T1 = P->T1;
-    r.T2 = P->T2;
+    r.T1 = P->T12;
+    r.T2 = nullptr;
     r.t_ld = P->ldw;
     r.r64 = Y;
     r.r64_ld = ldy;

@@ -84,8 +84,7 @@ struct hpadi_plan_s {
     double* T64 = nullptr;        // transform temporary (FP64, internal layout)
     // FP64 row-major work (mixed refinement, apply)
     long ldw = 0;
-    double* T1 = nullptr;
-    double* T2 = nullptr;
+    double* T12 = nullptr;        // row products U M_y, U A_y as interleaved pairs
     double* R64 = nullptr;
     double* H = nullptr;          // load temporary (Nleg_x x N_y)
     long ldh = 0;

@@ -151,7 +151,8 @@ hipError_t launch_op_apply(const DimDev& d, const OpApply& a, bool column, hipSt
 // (r64, may be NULL) and/or FP32 (r32, may be NULL); accumulates sum w r^2, sum w G^2.
 struct Residual {
     const double* G; long g_ld;
-    const double* T1; const double* T2; long t_ld;
+    const double* T1; const double* T2; long t_ld;  // T2 NULL: T1 holds (T1, T2) pairs, t_ld pairs
+                                                    // per row
     double* r64; long r64_ld;
     float* r32; long r32_ld;
     double ax_k, ax_t;   // A_x = ax_k K + ax_t M

@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256) op_apply_cols(DimDev d, OpApply a) {
 // rows); a thread takes RU rows at a time, whose taps are the same for every lane, and
 // issues all their loads before any store, so that RU rows of gathers are in flight at
 // once.  The weighted sums of squares are reduced per block (one atomic per sum).
-template <int NT>
+template <int NT, bool PAIRS>
 __device__ __forceinline__ void residual_rows(const DimDev& dx, const Residual& a, int j, int ibeg, int iend,
                                               double& sr, double& sg, double& su) {
     constexpr int RU = 4;
@@ -329,8 +329,16 @@ __device__ __forceinline__ void residual_rows(const DimDev& dx, const Residual& 
             double K1 = 0.0, M1 = 0.0, M2 = 0.0;
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
-                const double x1 = a.T1[(long)t.idx[q] * a.t_ld + j];
-                const double x2 = a.T2[(long)t.idx[q] * a.t_ld + j];
+                double x1, x2;
+                if constexpr (PAIRS) {
+                    // (T1, T2) interleaved: one 16-byte load per tap
+                    const double2 v = reinterpret_cast<const double2*>(a.T1)[(long)t.idx[q] * a.t_ld + j];
+                    x1 = v.x;
+                    x2 = v.y;
+                } else {
+                    x1 = a.T1[(long)t.idx[q] * a.t_ld + j];
+                    x2 = a.T2[(long)t.idx[q] * a.t_ld + j];
+                }
                 K1 += t.kc[q] * x1;
                 M1 += t.mc[q] * x1;
                 M2 += t.mc[q] * x2;
@@ -357,6 +365,7 @@ __device__ __forceinline__ void residual_rows(const DimDev& dx, const Residual& 
 }
 
 constexpr int kResRows = 4;  // rows per block: short-lived blocks, every load of a block in flight at once
+template <bool PAIRS>
 __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     __shared__ double red[3][4];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -369,10 +378,10 @@ __global__ void __launch_bounds__(256) residual_kernel(DimDev dx, Residual a) {
     if (j < a.ncols) {
         if ((int)blockIdx.y < hb) {
             const int ibeg = blockIdx.y * kResRows;
-            residual_rows<7>(dx, a, j, ibeg, min(dx.nh, ibeg + kResRows), sr, sg, su);
+            residual_rows<7, PAIRS>(dx, a, j, ibeg, min(dx.nh, ibeg + kResRows), sr, sg, su);
         } else {
             const int ibeg = dx.nh + (blockIdx.y - hb) * kResRows;
-            residual_rows<5>(dx, a, j, ibeg, min(dx.N, ibeg + kResRows), sr, sg, su);
+            residual_rows<5, PAIRS>(dx, a, j, ibeg, min(dx.N, ibeg + kResRows), sr, sg, su);
         }
     }
     if (a.norm_acc) {
@@ -535,7 +544,8 @@ long residual_partials(const DimDev& dx, int ncols) {
 hipError_t launch_residual(const DimDev& dx, const Residual& a, hipStream_t s) {
     if (a.ncols <= 0 || dx.N <= 0) return hipSuccess;
     const dim3 g = residual_grid(dx, a.ncols);
-    hipLaunchKernelGGL(residual_kernel, g, dim3(256), 0, s, dx, a);
+    if (a.T2) hipLaunchKernelGGL(residual_kernel<false>, g, dim3(256), 0, s, dx, a);
+    else hipLaunchKernelGGL(residual_kernel<true>, g, dim3(256), 0, s, dx, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.norm_acc || !a.partials) return e;
     const int nblk = (int)(g.x * g.y), nk = a.U ? 3 : 2;
